@@ -1,0 +1,236 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) PC-LSQR hot path of the Gaia AVU-GSR solver
+ * (arXiv 2212.11675).
+ *
+ * The library solves  min || A x - b ||_2  for the astrometric observation matrix A of
+ * Section 3 of the paper, stored in its compressed row form ("A_d", 24 coefficients per
+ * row) with the per-row index map ("M_i": star number and attitude start; "I_c": six
+ * instrumental indices).  Column order of the unknowns x (Section 3):
+ *
+ *     [ astrometric 5*n_stars | attitude 3*n_dfa | instrumental n_instr | global 1 ]
+ *
+ * Row i, slot k of `vals` (k = 0..23) multiplies
+ *     k = 0..4    : x[5*star[i] + k]
+ *     k = 5..16   : x[5*n_stars + a*n_dfa + att[i] + j],  a = (k-5)/4, j = (k-5)%4
+ *     k = 17..22  : x[5*n_stars + 3*n_dfa + instr[6*i + (k-17)]]
+ *     k = 23      : x[5*n_stars + 3*n_dfa + n_instr]
+ * (index expressions of Algorithm 1; att and instr are stored relative to their section).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors) unless the
+ *     comment says "host".  The caller owns them.  Buffers passed to gsr_lsqr_setup /
+ *     gsr_batch_setup are referenced, not copied, and must stay valid and unchanged until
+ *     the matching destroy call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are stream-ordered and
+ *     asynchronous except where the comment says the call synchronizes.
+ *   - Errors are returned as gsr_status; nothing aborts or exits.  Arguments are checked on
+ *     the host before any device work; gsr_last_error() gives a message for the last
+ *     failing call on the calling thread.
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_ABI_VERSION 1
+
+typedef enum gsr_status {
+    GSR_OK = 0,
+    GSR_E_INVAL = -1,       /* bad argument: null pointer, negative or inconsistent size   */
+    GSR_E_LAYOUT = -2,      /* matrix data violates the layout (index out of range, stars
+                               not sorted, all-zero column when not allowed)              */
+    GSR_E_NOMEM = -3,       /* device allocation failed                                    */
+    GSR_E_HIP = -4,         /* a HIP runtime call failed                                   */
+    GSR_E_BREAKDOWN = -5,   /* non-finite value met inside the iteration                   */
+    GSR_E_UNSUPPORTED = -6, /* valid request this build does not support                   */
+    GSR_E_NODEVICE = -7     /* no usable gfx950 device                                     */
+} gsr_status;
+
+/* Sizes of one system (Section 3).  n_glob must be 1 (the PPN gamma column), n_dfa >= 4
+ * (one 4-wide B-spline block per attitude axis), n_instr >= 6 (six distinct instrumental
+ * columns per row).  n_cols = 5*n_stars + 3*n_dfa + n_instr + n_glob. */
+typedef struct gsr_dims {
+    int64_t n_rows;
+    int64_t n_stars;
+    int32_t n_dfa;
+    int32_t n_instr;
+    int32_t n_glob;
+} gsr_dims;
+
+typedef enum gsr_precision {
+    GSR_F64 = 0, /* coefficients read as stored (binary64)                              */
+    GSR_F32V = 1 /* coefficients read from a binary32 copy, binary64 accumulation, with
+                    binary64 residual correction around the inner solves                */
+} gsr_precision;
+
+typedef struct gsr_setup_opts {
+    int32_t build_f32;        /* 1: also build the library-owned binary32 coefficient copy
+                                 (needed by the GSR_F32V entry points)                   */
+    int32_t validate;         /* 1: check index ranges and star order on the device      */
+    int32_t allow_empty_cols; /* 1: accept all-zero columns (their unknown is set to 0);
+                                 0: such a column makes setup fail with GSR_E_LAYOUT      */
+    int32_t reserved;
+} gsr_setup_opts;
+
+typedef struct gsr_solve_opts {
+    int32_t itnlim;      /* maximum LSQR iterations (per inner solve in the F32V form)    */
+    int32_t fixed_iters; /* 1: run exactly itnlim iterations; only an exact breakdown
+                            (alpha or beta = 0) ends the iteration earlier               */
+    double atol, btol;   /* Paige-Saunders tests, used when fixed_iters = 0:
+                            ||r|| <= btol ||b|| + atol ||A D|| ||z||  or
+                            ||(A D)^T r|| <= atol ||A D|| ||r||                          */
+    int32_t precision;   /* gsr_precision                                                 */
+    int32_t max_refine;  /* GSR_F32V: maximum outer residual-correction steps (>= 1)      */
+    double refine_tol;   /* GSR_F32V: stop when ||dx|| <= refine_tol ||x||                */
+    int32_t check_every; /* iterations between host reads of the stop flag (0 = 16)       */
+    int32_t profile;     /* 1: launch the iterations one by one (no graph) with HIP events
+                            around every product; averages go to gsr_solve_info           */
+} gsr_solve_opts;
+
+typedef struct gsr_solve_info {
+    int32_t itn;      /* LSQR iterations performed (summed over refinement steps)          */
+    int32_t istop;    /* 0 itnlim reached, 1 compatible-system test, 2 least-squares test,
+                         3 exact breakdown, 4 zero right-hand side                         */
+    int32_t n_refine; /* outer steps taken (GSR_F32V), 1 otherwise                         */
+    int32_t reserved;
+    double rnorm;     /* estimate of ||b - A x|| (last inner solve)                        */
+    double arnorm;    /* estimate of ||(A D)^T r||                                         */
+    double anorm;     /* Frobenius estimate of ||A D||                                      */
+    double znorm;     /* ||z||, z = x / p the preconditioned unknowns                      */
+    double bnorm;     /* ||b|| (of the last inner right-hand side)                         */
+    double ms_aprod1; /* profile = 1: mean duration of one aprod 1 launch in the iterations  */
+    double ms_aprod2; /* profile = 1: mean duration of one aprod 2 launch in the iterations  */
+    int32_t n_aprod1; /* number of launches averaged                                         */
+    int32_t n_aprod2;
+} gsr_solve_info;
+
+typedef struct gsr_handle gsr_handle;
+
+/* ABI version this library was built with (GSR_ABI_VERSION). */
+int32_t gsr_abi_version(void);
+
+/* Text for a status code; static storage. */
+const char *gsr_status_string(gsr_status s);
+
+/* Message for the last failing call on this thread ("" if none); thread-local storage. */
+const char *gsr_last_error(void);
+
+/*
+ * Set up a system for the products and the solver (Section 3 layout, Section 2
+ * column-norm preconditioning).
+ *   dims   host; sizes as above.
+ *   vals   [n_rows*24] binary64, row-major in the slot order above.
+ *   star   [n_rows] int32, non-decreasing, in [0, n_stars)  (rows sorted by star).
+ *   att    [n_rows] int32 in [0, n_dfa-4]: attitude start relative to the section.
+ *   instr  [n_rows*6] int32 in [0, n_instr): instrumental indices relative to the section.
+ *   opts   host, may be NULL (defaults: no f32 copy, validate, reject empty columns).
+ *   out    host; receives the handle.
+ * Computes the preconditioner p_j = 1/||A e_j||_2 (0 for an all-zero column) on the device.
+ * Synchronizes `stream`.  Errors: GSR_E_INVAL, GSR_E_LAYOUT, GSR_E_NOMEM, GSR_E_HIP,
+ * GSR_E_NODEVICE.
+ */
+gsr_status gsr_lsqr_setup(const gsr_dims *dims, const double *vals, const int32_t *star,
+                          const int32_t *att, const int32_t *instr, const gsr_setup_opts *opts,
+                          void *stream, gsr_handle **out);
+
+/* Release the handle and everything it owns.  NULL is accepted. */
+gsr_status gsr_destroy(gsr_handle *h);
+
+/* Sizes of the handle's system (host out-pointers, any may be NULL). */
+gsr_status gsr_get_size(const gsr_handle *h, int64_t *n_rows, int64_t *n_cols);
+
+/* aprod mode 1 (Section 3; Algorithm 1):  y[i] += sum_k A[i,k] x[col(i,k)].
+ *   x [n_cols], y [n_rows], binary64; y is read and written.  Unpreconditioned A. */
+gsr_status gsr_aprod1(gsr_handle *h, const double *x, double *y, void *stream);
+
+/* aprod mode 2 (Section 3; Algorithm 2):  x[col(i,k)] += A[i,k] y[i]  (x += A^T y).
+ *   y [n_rows], x [n_cols], binary64; x is read and written.  Unpreconditioned A.
+ *   Summation order varies between calls (device atomics): results agree to rounding. */
+gsr_status gsr_aprod2(gsr_handle *h, const double *y, double *x, void *stream);
+
+/* The same two products with the binary32 coefficient copy (setup with build_f32 = 1),
+ * products and sums in binary64.  GSR_E_UNSUPPORTED if the copy was not built. */
+gsr_status gsr_aprod1_f32v(gsr_handle *h, const double *x, double *y, void *stream);
+gsr_status gsr_aprod2_f32v(gsr_handle *h, const double *y, double *x, void *stream);
+
+/* Copy the preconditioner p [n_cols] (Section 2: reciprocal column norms) into `p`
+ * (device).  `precision` selects the factors of the binary64 or the binary32 coefficients. */
+gsr_status gsr_precond(gsr_handle *h, int32_t precision, double *p, void *stream);
+
+/* r = b - A x with the binary64 coefficients.  b, r [n_rows]; x [n_cols]. */
+gsr_status gsr_residual(gsr_handle *h, const double *b, const double *x, double *r,
+                        void *stream);
+
+/*
+ * PC-LSQR (Section 3 flowchart; LSQR of Paige & Saunders 1982 on A D, D = diag(p),
+ * x = p o z at the end).  b [n_rows], x [n_cols] output (the caller's buffer, overwritten).
+ * opts host (NULL: 100 iterations, fixed, binary64); info host, may be NULL.
+ * GSR_F32V runs  x_0 = 0, r_0 = b;  d_k = PC-LSQR(A_32, r_k);  x_{k+1} = x_k + d_k;
+ * r_{k+1} = b - A x_{k+1} (binary64 coefficients) until ||d_k|| <= refine_tol ||x_{k+1}||
+ * or max_refine steps.  Synchronizes `stream` (to read the stop flag and fill info).
+ */
+gsr_status gsr_lsqr_solve(gsr_handle *h, const double *b, double *x, const gsr_solve_opts *opts,
+                          gsr_solve_info *info, void *stream);
+
+/*
+ * Adjoint of the least-squares solve, for a loss L(x*) with g = dL/dx* [n_cols]:
+ *   mu  [n_rows] = minimum-norm solution of A^T mu = g  (LSQR on D A^T, rhs D g) = dL/db,
+ *   lam [n_cols] = argmin || A lam - mu ||               (PC-LSQR)  = (A^T A)^{-1} g.
+ * opts as for gsr_lsqr_solve (binary64 only); info (host, may be NULL) receives two entries
+ * (info[0] for mu, info[1] for lam).  Synchronizes `stream`.
+ */
+gsr_status gsr_lsqr_solve_adjoint(gsr_handle *h, const double *g, double *mu, double *lam,
+                                  const gsr_solve_opts *opts, gsr_solve_info *info,
+                                  void *stream);
+
+/* dL/dvals[i*24+k] = r[i] lam[col(i,k)] - mu[i] x[col(i,k)]  (differentiating the normal
+ * equations A^T A x = A^T b), with r = b - A x*.  r, mu [n_rows]; x, lam [n_cols];
+ * dvals [n_rows*24] output. */
+gsr_status gsr_grad_vals(gsr_handle *h, const double *r, const double *mu, const double *x,
+                         const double *lam, double *dvals, void *stream);
+
+/* ---- batching: many independent systems, k right-hand sides each ------------------------ */
+
+typedef struct gsr_batch gsr_batch;
+
+/*
+ * Set up n_sys independent systems stored back to back.
+ *   dims        host [n_sys].
+ *   row_offset  host [n_sys+1]: system s owns rows row_offset[s] .. row_offset[s+1]-1 of
+ *               the concatenated arrays (row_offset[0] = 0).
+ *   vals/star/att/instr  device, concatenated; indices are relative to each system.
+ *   k           right-hand sides per system, 1..8.
+ * Unknowns of system s occupy columns col_offset[s] .. col_offset[s+1]-1 of the batched
+ * unknown vector (gsr_batch_col_offsets), each system in the column order above.
+ * Synchronizes `stream`.
+ */
+gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims *dims, const int64_t *row_offset,
+                           const double *vals, const int32_t *star, const int32_t *att,
+                           const int32_t *instr, int32_t k, const gsr_setup_opts *opts,
+                           void *stream, gsr_batch **out);
+gsr_status gsr_batch_destroy(gsr_batch *b);
+
+/* host out [n_sys+1] */
+gsr_status gsr_batch_col_offsets(const gsr_batch *b, int64_t *col_offset);
+
+/* Multi-RHS products over all systems at once (RHS-minor storage, element (row, j) at
+ * row*k + j):  Y[i, j] += sum A[i,c] X[c, j]  and  X[c, j] += sum A[i,c] Y[i, j]. */
+gsr_status gsr_batch_aprod1(gsr_batch *b, const double *X, double *Y, void *stream);
+gsr_status gsr_batch_aprod2(gsr_batch *b, const double *Y, double *X, void *stream);
+
+/* PC-LSQR of every (system, rhs) pair: B [sum rows * k], X [sum cols * k] output, both
+ * RHS-minor; each pair has its own scalars and stopping state.  info host [n_sys*k] or
+ * NULL (entry s*k + j).  Synchronizes `stream`. */
+gsr_status gsr_batch_solve(gsr_batch *b, const double *B, double *X, const gsr_solve_opts *opts,
+                           gsr_solve_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

@@ -1,0 +1,766 @@
+// C ABI of the PC-LSQR hot path (declarations and contracts in include/gsr.h).
+//
+// One handle = one system whose coefficient and index arrays stay in the caller's device
+// buffers.  The handle owns the preconditioner, the optional binary32 coefficient copy and
+// the LSQR work vectors; every LSQR scalar lives in device memory (LsqrState), so an
+// iteration is a fixed sequence of kernels that is captured once in a hipGraph and
+// replayed; the host only reads the stop flag between replays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsr.h"
+#include "gsr_internal.hpp"
+#include "kernels.hpp"
+
+using namespace gsr;
+
+namespace gsr {
+
+thread_local std::string g_last_error;
+
+gsr_status fail(gsr_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+gsr_status hip_fail(hipError_t e, const char* what) {
+    return fail(GSR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+gsr_status check_device(int* dev, int* n_cu) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(GSR_E_NODEVICE, "no HIP device visible");
+    e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, *dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GSR_E_NODEVICE, "device %d is %s; this library is built for gfx950", *dev,
+                    prop.gcnArchName);
+    *n_cu = prop.multiProcessorCount;
+    return GSR_OK;
+}
+
+gsr_status check_dims(const gsr_dims* d) {
+    if (!d) return fail(GSR_E_INVAL, "dims is NULL");
+    if (d->n_rows < 0) return fail(GSR_E_INVAL, "n_rows < 0");
+    if (d->n_stars < 1) return fail(GSR_E_INVAL, "n_stars < 1");
+    if (d->n_dfa < kParAxis) return fail(GSR_E_INVAL, "n_dfa < 4");
+    if (d->n_instr < kInstr) return fail(GSR_E_INVAL, "n_instr < 6");
+    if (d->n_glob != 1) return fail(GSR_E_UNSUPPORTED, "n_glob must be 1");
+    if (d->n_stars > (int64_t)INT32_MAX / kAstro)
+        return fail(GSR_E_UNSUPPORTED, "n_stars too large for int32 star indices");
+    return GSR_OK;
+}
+
+Geo make_geo(const gsr_dims* d) {
+    Geo g;
+    g.m = d->n_rows;
+    g.n_stars = d->n_stars;
+    g.T = d->n_dfa;
+    g.I = d->n_instr;
+    g.att0 = (int64_t)kAstro * d->n_stars;
+    g.ins0 = g.att0 + (int64_t)kAxes * d->n_dfa;
+    g.glb0 = g.ins0 + d->n_instr;
+    g.n = g.glb0 + d->n_glob;
+    return g;
+}
+
+int grid_for(int64_t items, int per_block, int max_blocks) {
+    const int64_t b = (items + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, max_blocks));
+}
+
+}  // namespace gsr
+
+#define HIP_TRY(call)                                      \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+    } while (0)
+
+#define GSR_TRY(call)                     \
+    do {                                  \
+        gsr_status s_ = (call);           \
+        if (s_ != GSR_OK) return s_;      \
+    } while (0)
+
+namespace {
+
+// Workspace of one LSQR recurrence over an operator with `rows` x `cols`.
+struct LsqrWork {
+    int64_t rows = 0, cols = 0;
+    double *u = nullptr, *v = nullptr, *w = nullptr, *z = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_iters = 0;
+};
+
+}  // namespace
+
+struct gsr_handle {
+    int device = 0;
+    int n_cu = 256;
+    Geo g;
+    const double* vals = nullptr;
+    const int32_t *star = nullptr, *att = nullptr, *instr = nullptr;
+    float* vals32 = nullptr;
+    double *p64 = nullptr, *p32 = nullptr;
+    double* s = nullptr;       // [n] aprod 2 accumulator (kept zero between uses)
+    double *partA = nullptr, *partB = nullptr;
+    LsqrState* st = nullptr;   // device scalars
+    LsqrState* st_host = nullptr;  // pinned mirror
+    int G1 = 1, G2 = 1, Gn = 1, Gm = 1;
+    int lds_instr = 0;
+    size_t lds2 = 0;
+    LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
+    double *dx = nullptr, *r = nullptr;  // refinement
+    hipStream_t cap = nullptr;     // capture stream
+};
+
+namespace {
+
+constexpr int kVecBlocksMax = 2048;
+constexpr int kRowBlocksMax = 8192;
+constexpr int kGraphIters = 16;
+
+template <typename T>
+gsr_status dalloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(GSR_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return GSR_OK;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+void free_work(LsqrWork& w) {
+    if (w.graph) (void)hipGraphExecDestroy(w.graph);
+    dfree(w.u);
+    dfree(w.v);
+    dfree(w.w);
+    dfree(w.z);
+    w = LsqrWork();
+}
+
+gsr_status ensure_work(LsqrWork& w, int64_t rows, int64_t cols) {
+    if (w.u) return GSR_OK;
+    w.rows = rows;
+    w.cols = cols;
+    GSR_TRY(dalloc(&w.u, rows));
+    GSR_TRY(dalloc(&w.v, cols));
+    GSR_TRY(dalloc(&w.w, cols));
+    GSR_TRY(dalloc(&w.z, cols));
+    return GSR_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+void fill(double* v, int64_t n, double val, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, kVecBlocksMax)), dim3(kBlock), 0, s, v,
+                       n, val);
+}
+
+// ---- launches of the products --------------------------------------------------------
+
+template <typename VT, int MODE, bool PRE>
+void launch_aprod1(const gsr_handle* h, const VT* vals, const double* x, const double* p,
+                   double* y, const double* b, hipStream_t s) {
+    hipLaunchKernelGGL((k_aprod1<VT, MODE, PRE>), dim3(h->G1), dim3(kBlock), 0, s, h->g, vals,
+                       h->star, h->att, h->instr, x, p, y, b, h->st, h->partA);
+}
+
+template <typename VT, int MODE>
+void launch_aprod2(const gsr_handle* h, const VT* vals, const double* y, double* x,
+                   hipStream_t s) {
+    hipLaunchKernelGGL((k_aprod2<VT, MODE>), dim3(h->G2), dim3(kBlock), h->lds2, s, h->g, vals,
+                       h->star, h->att, h->instr, y, x, h->st, h->lds_instr);
+}
+
+// p = 1 / column norms of `vals`.  Synchronizes.
+template <typename VT>
+gsr_status colnorm(gsr_handle* h, const VT* vals, double* p, hipStream_t s,
+                   unsigned long long* n_empty) {
+    unsigned long long* d_cnt = nullptr;
+    GSR_TRY(dalloc(&d_cnt, 1));
+    HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(*d_cnt), s));
+    fill(h->s, h->g.n, 0.0, s);
+    launch_aprod2<VT, A2_SQ>(h, vals, nullptr, h->s, s);
+    hipLaunchKernelGGL(k_recip_sqrt, dim3(grid_for(h->g.n, kBlock, kVecBlocksMax)), dim3(kBlock),
+                       0, s, h->g.n, h->s, p, d_cnt);
+    hipError_t e = hipMemcpyAsync(n_empty, d_cnt, sizeof(*d_cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(d_cnt);
+    if (e != hipSuccess) return hip_fail(e, "column norms");
+    return GSR_OK;
+}
+
+// ---- one forward PC-LSQR iteration: u- and v-steps, Givens, vector updates -------------
+
+// Events bracketing the two products of one iteration (profile mode only).
+struct IterEvents {
+    hipEvent_t a1_begin, a1_end, a2_begin, a2_end;
+};
+
+void mark(hipEvent_t e, hipStream_t s) {
+    if (e) (void)hipEventRecord(e, s);
+}
+
+template <typename VT>
+void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const double* p,
+                   hipStream_t s, const IterEvents* ev = nullptr) {
+    const Geo& g = h->g;
+    // beta u = A (p o v) - alpha u
+    if (ev) mark(ev->a1_begin, s);
+    launch_aprod1<VT, A1_LSQR, true>(h, vals, w.v, p, w.u, nullptr, s);
+    if (ev) mark(ev->a1_end, s);
+    hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+    // alpha v = p o A^T u - beta v, with the pending z/w update of the previous iteration
+    if (ev) mark(ev->a2_begin, s);
+    launch_aprod2<VT, A2_LSQR>(h, vals, w.u, h->s, s);
+    if (ev) mark(ev->a2_end, s);
+    hipLaunchKernelGGL(k_vec_v<false>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
+                       w.z, h->st, h->partB);
+    hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn,
+                       h->partB + h->Gn, h->Gn);
+}
+
+// Transposed operator B = D A^T (rows = n_cols, cols = n_rows): u lives in the unknowns'
+// space, v / w / z in the observations' space.
+void trans_iteration(const gsr_handle* h, LsqrWork& w, hipStream_t s,
+                     const IterEvents* ev = nullptr) {
+    const Geo& g = h->g;
+    // beta u = D A^T v - alpha u
+    if (ev) mark(ev->a2_begin, s);
+    launch_aprod2<double, A2_LSQR_T>(h, h->vals, w.v, h->s, s);
+    if (ev) mark(ev->a2_end, s);
+    hipLaunchKernelGGL(k_vec_tu, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, h->p64, w.u, h->st,
+                       h->partA);
+    hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn);
+    // pending z/w update, then alpha v = A D u - beta v
+    hipLaunchKernelGGL(k_vec_zw, dim3(h->Gm), dim3(kBlock), 0, s, g.m, w.v, w.w, w.z, h->st,
+                       h->partB);
+    if (ev) mark(ev->a1_begin, s);
+    launch_aprod1<double, A1_LSQR_T, true>(h, h->vals, w.u, h->p64, w.v, nullptr, s);
+    if (ev) mark(ev->a1_end, s);
+    hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1,
+                       h->partB, h->Gm);
+}
+
+// Profile mode: the iterations are launched one by one with events around the products;
+// mean durations over the iterations actually performed go to `info`.  Synchronizes.
+template <typename F>
+gsr_status run_profiled(gsr_handle* h, const gsr_solve_opts& o, hipStream_t s, F&& iteration,
+                        double* ms1, double* ms2, int* n_done) {
+    std::vector<IterEvents> ev((size_t)o.itnlim);
+    for (auto& e : ev) {
+        HIP_TRY(hipEventCreate(&e.a1_begin));
+        HIP_TRY(hipEventCreate(&e.a1_end));
+        HIP_TRY(hipEventCreate(&e.a2_begin));
+        HIP_TRY(hipEventCreate(&e.a2_end));
+    }
+    const int every = o.check_every > 0 ? o.check_every : 16;
+    int launched = 0;
+    gsr_status rc = GSR_OK;
+    for (int it = 0; it < o.itnlim; ++it) {
+        iteration(s, &ev[(size_t)it]);
+        ++launched;
+        if (!o.fixed_iters && (it + 1) % every == 0) {
+            hipError_t e = hipMemcpyAsync(&h->st_host->stop, &h->st->stop, sizeof(int32_t),
+                                          hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "stop flag");
+                break;
+            }
+            if (h->st_host->stop) break;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(h->st_host, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess && rc == GSR_OK) rc = hip_fail(e, "profile sync");
+    const int done = std::min(launched, (int)h->st_host->itn);
+    double t1 = 0.0, t2 = 0.0;
+    for (int it = 0; rc == GSR_OK && it < done; ++it) {
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, ev[(size_t)it].a1_begin, ev[(size_t)it].a1_end);
+        (void)hipEventElapsedTime(&b, ev[(size_t)it].a2_begin, ev[(size_t)it].a2_end);
+        t1 += a;
+        t2 += b;
+    }
+    for (auto& x : ev) {
+        (void)hipEventDestroy(x.a1_begin);
+        (void)hipEventDestroy(x.a1_end);
+        (void)hipEventDestroy(x.a2_begin);
+        (void)hipEventDestroy(x.a2_end);
+    }
+    *n_done = done;
+    *ms1 = done ? t1 / done : 0.0;
+    *ms2 = done ? t2 / done : 0.0;
+    return rc;
+}
+
+template <typename F>
+gsr_status capture_graph(gsr_handle* h, LsqrWork& w, F&& body) {
+    if (w.graph) return GSR_OK;
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kGraphIters; ++k) body(h->cap);
+    hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        w.graph = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    w.graph_iters = kGraphIters;
+    return GSR_OK;
+}
+
+// Replays the iteration graph until the device stop flag is set (or itnlim is reached).
+gsr_status run_iterations(gsr_handle* h, LsqrWork& w, const gsr_solve_opts& o, hipStream_t s) {
+    const int per_check = std::max(1, (o.check_every > 0 ? o.check_every : 16) / w.graph_iters);
+    int done = 0;
+    while (done < o.itnlim) {
+        for (int k = 0; k < per_check && done < o.itnlim; ++k) {
+            HIP_TRY(hipGraphLaunch(w.graph, s));
+            done += w.graph_iters;
+        }
+        if (o.fixed_iters || done >= o.itnlim) continue;
+        HIP_TRY(hipMemcpyAsync(&h->st_host->stop, &h->st->stop, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h->st_host->stop) break;
+    }
+    return GSR_OK;
+}
+
+struct ProfileOut {
+    double ms1 = 0.0, ms2 = 0.0;
+    int n = 0;
+};
+
+gsr_status read_info(gsr_handle* h, gsr_solve_info* info, hipStream_t s,
+                     const ProfileOut& prof) {
+    HIP_TRY(hipMemcpyAsync(h->st_host, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const LsqrState& t = *h->st_host;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->ms_aprod1 = prof.ms1;
+        info->ms_aprod2 = prof.ms2;
+        info->n_aprod1 = prof.n;
+        info->n_aprod2 = prof.n;
+        info->itn = t.itn;
+        info->istop = t.istop;
+        info->n_refine = 1;
+        info->rnorm = t.rnorm;
+        info->arnorm = t.arnorm;
+        info->anorm = std::sqrt(t.anorm2);
+        info->znorm = std::sqrt(t.znorm2);
+        info->bnorm = t.bnorm;
+    }
+    if (t.nonfinite) return fail(GSR_E_BREAKDOWN, "non-finite value in the LSQR recurrence");
+    return GSR_OK;
+}
+
+// PC-LSQR on A (binary64 or binary32 coefficients): x = p o z.  Synchronizes.
+template <typename VT>
+gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const double* p,
+                     const double* b, double* x, const gsr_solve_opts& o, gsr_solve_info* info,
+                     hipStream_t s) {
+    const Geo& g = h->g;
+    GSR_TRY(ensure_work(w, g.m, g.n));
+    GSR_TRY(capture_graph(h, w, [&](hipStream_t cs) { fwd_iteration<VT>(h, w, vals, p, cs); }));
+    // beta_1 u_1 = b
+    hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
+                       w.u, h->partA);
+    hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gm,
+                       o.itnlim, o.fixed_iters, o.atol, o.btol);
+    // alpha_1 v_1 = p o A^T u_1  (the initial aprod 2)
+    fill(h->s, g.n, 0.0, s);
+    launch_aprod2<VT, A2_LSQR>(h, vals, w.u, h->s, s);
+    hipLaunchKernelGGL(k_vec_v<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
+                       w.z, h->st, h->partB);
+    hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
+    ProfileOut prof;
+    if (o.profile)
+        GSR_TRY(run_profiled(
+            h, o, s,
+            [&](hipStream_t cs, const IterEvents* ev) { fwd_iteration<VT>(h, w, vals, p, cs, ev); },
+            &prof.ms1, &prof.ms2, &prof.n));
+    else
+        GSR_TRY(run_iterations(h, w, o, s));
+    hipLaunchKernelGGL(k_final<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, p, w.z, w.w, w.v, x,
+                       h->st);
+    HIP_TRY(hipGetLastError());
+    return read_info(h, info, s, prof);
+}
+
+gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_solve_opts& o,
+                       gsr_solve_info* info, hipStream_t s) {
+    const Geo& g = h->g;
+    LsqrWork& w = h->trans;
+    GSR_TRY(ensure_work(w, g.n, g.m));
+    GSR_TRY(capture_graph(h, w, [&](hipStream_t cs) { trans_iteration(h, w, cs); }));
+    // beta_1 u_1 = D g
+    hipLaunchKernelGGL(k_copy_norm<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, gvec, h->p64,
+                       w.u, h->partA);
+    hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn,
+                       o.itnlim, o.fixed_iters, o.atol, o.btol);
+    // alpha_1 v_1 = A D u_1
+    launch_aprod1<double, A1_LSQR_T, true>(h, h->vals, w.u, h->p64, w.v, nullptr, s);
+    fill(w.w, g.m, 0.0, s);
+    fill(w.z, g.m, 0.0, s);
+    hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+    ProfileOut prof;
+    if (o.profile)
+        GSR_TRY(run_profiled(
+            h, o, s, [&](hipStream_t cs, const IterEvents* ev) { trans_iteration(h, w, cs, ev); },
+            &prof.ms1, &prof.ms2, &prof.n));
+    else
+        GSR_TRY(run_iterations(h, w, o, s));
+    hipLaunchKernelGGL(k_final<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, nullptr, w.z, w.w,
+                       w.v, mu, h->st);
+    HIP_TRY(hipGetLastError());
+    return read_info(h, info, s, prof);
+}
+
+gsr_solve_opts default_opts() {
+    gsr_solve_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.itnlim = 100;
+    o.fixed_iters = 1;
+    o.atol = 1e-14;
+    o.btol = 1e-14;
+    o.precision = GSR_F64;
+    o.max_refine = 4;
+    o.refine_tol = 1e-10;
+    return o;
+}
+
+gsr_status check_opts(const gsr_solve_opts& o) {
+    if (o.itnlim < 0) return fail(GSR_E_INVAL, "itnlim < 0");
+    if (!(o.atol >= 0) || !(o.btol >= 0)) return fail(GSR_E_INVAL, "atol/btol must be >= 0");
+    if (o.precision != GSR_F64 && o.precision != GSR_F32V)
+        return fail(GSR_E_INVAL, "unknown precision %d", o.precision);
+    if (o.precision == GSR_F32V && o.max_refine < 1) return fail(GSR_E_INVAL, "max_refine < 1");
+    return GSR_OK;
+}
+
+gsr_status set_device(const gsr_handle* h) {
+    HIP_TRY(hipSetDevice(h->device));
+    return GSR_OK;
+}
+
+}  // namespace
+
+// =======================================================================================
+// C ABI
+
+extern "C" {
+
+int32_t gsr_abi_version(void) { return GSR_ABI_VERSION; }
+
+const char* gsr_status_string(gsr_status s) {
+    switch (s) {
+        case GSR_OK: return "ok";
+        case GSR_E_INVAL: return "invalid argument";
+        case GSR_E_LAYOUT: return "matrix layout violated";
+        case GSR_E_NOMEM: return "device allocation failed";
+        case GSR_E_HIP: return "HIP runtime error";
+        case GSR_E_BREAKDOWN: return "non-finite value in the iteration";
+        case GSR_E_UNSUPPORTED: return "unsupported";
+        case GSR_E_NODEVICE: return "no gfx950 device";
+    }
+    return "unknown status";
+}
+
+const char* gsr_last_error(void) { return g_last_error.c_str(); }
+
+gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_t* star,
+                          const int32_t* att, const int32_t* instr, const gsr_setup_opts* opts,
+                          void* stream, gsr_handle** out) {
+    g_last_error.clear();
+    if (!out) return fail(GSR_E_INVAL, "out is NULL");
+    *out = nullptr;
+    GSR_TRY(check_dims(dims));
+    if (dims->n_rows > 0 && (!vals || !star || !att || !instr))
+        return fail(GSR_E_INVAL, "null matrix array");
+    if (((uintptr_t)vals & 15) || ((uintptr_t)instr & 7))
+        return fail(GSR_E_INVAL, "vals must be 16-byte and instr 8-byte aligned");
+    gsr_setup_opts so = {0, 1, 0, 0};
+    if (opts) so = *opts;
+
+    int dev = 0, n_cu = 0;
+    GSR_TRY(check_device(&dev, &n_cu));
+    hipStream_t s = as_stream(stream);
+
+    gsr_handle* h = new gsr_handle();
+    h->device = dev;
+    h->n_cu = n_cu;
+    h->g = make_geo(dims);
+    h->vals = vals;
+    h->star = star;
+    h->att = att;
+    h->instr = instr;
+    const Geo& g = h->g;
+    auto bail = [&](gsr_status st) {
+        gsr_destroy(h);
+        return st;
+    };
+
+    h->G1 = grid_for(g.m, kBlock, kRowBlocksMax);
+    h->Gn = grid_for(g.n, kBlock, kVecBlocksMax);
+    h->Gm = grid_for(g.m, kBlock, kVecBlocksMax);
+    h->lds_instr = g.I <= kInstrLdsMax;
+    h->lds2 = sizeof(double) * ((h->lds_instr ? g.I : 0) + 1);
+    {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_aprod2<double, A2_LSQR>, kBlock, h->lds2);
+        if (e != hipSuccess || per_cu < 1) per_cu = 1;
+        const int64_t tiles = (g.m + kBlock - 1) / kBlock;
+        h->G2 = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)per_cu * n_cu));
+    }
+    gsr_status st;
+    if ((st = dalloc(&h->p64, g.n)) != GSR_OK) return bail(st);
+    if ((st = dalloc(&h->s, g.n)) != GSR_OK) return bail(st);
+    const int part_len = std::max(std::max(h->G1, h->Gm), h->Gn);
+    if ((st = dalloc(&h->partA, part_len)) != GSR_OK) return bail(st);
+    if ((st = dalloc(&h->partB, 4 * (size_t)part_len)) != GSR_OK) return bail(st);
+    if ((st = dalloc(&h->st, 1)) != GSR_OK) return bail(st);
+    {
+        hipError_t e = hipHostMalloc((void**)&h->st_host, sizeof(LsqrState), hipHostMallocDefault);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+        e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
+    }
+
+    if (so.validate && g.m > 0) {
+        int* d_flags = nullptr;
+        if ((st = dalloc(&d_flags, 1)) != GSR_OK) return bail(st);
+        int flags = 0;
+        hipError_t e = hipMemsetAsync(d_flags, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_validate, dim3(grid_for(g.m, kBlock, kVecBlocksMax)),
+                               dim3(kBlock), 0, s, g, star, att, instr, d_flags);
+            e = hipMemcpyAsync(&flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dfree(d_flags);
+        if (e != hipSuccess) return bail(hip_fail(e, "validation"));
+        if (flags)
+            return bail(fail(GSR_E_LAYOUT,
+                             "index check failed:%s%s%s%s", (flags & 1) ? " star out of range" : "",
+                             (flags & 2) ? " stars not sorted" : "",
+                             (flags & 4) ? " attitude start out of [0, n_dfa-4]" : "",
+                             (flags & 8) ? " instrumental index out of range" : ""));
+    }
+    unsigned long long n_empty = 0;
+    if ((st = colnorm<double>(h, vals, h->p64, s, &n_empty)) != GSR_OK) return bail(st);
+    if (n_empty && !so.allow_empty_cols)
+        return bail(fail(GSR_E_LAYOUT, "%llu all-zero column(s); set allow_empty_cols", n_empty));
+    if (so.build_f32) {
+        if ((st = dalloc(&h->vals32, (size_t)g.m * kPar)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->p32, g.n)) != GSR_OK) return bail(st);
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for((int64_t)g.m * kPar, kBlock, 8192)),
+                           dim3(kBlock), 0, s, (int64_t)g.m * kPar, vals, h->vals32);
+        unsigned long long n_empty32 = 0;
+        if ((st = colnorm<float>(h, h->vals32, h->p32, s, &n_empty32)) != GSR_OK) return bail(st);
+    }
+    *out = h;
+    return GSR_OK;
+}
+
+gsr_status gsr_destroy(gsr_handle* h) {
+    if (!h) return GSR_OK;
+    (void)hipSetDevice(h->device);
+    if (h->cap) (void)hipStreamSynchronize(h->cap);
+    (void)hipDeviceSynchronize();
+    free_work(h->fwd64);
+    free_work(h->fwd32);
+    free_work(h->trans);
+    dfree(h->vals32);
+    dfree(h->p64);
+    dfree(h->p32);
+    dfree(h->s);
+    dfree(h->partA);
+    dfree(h->partB);
+    dfree(h->st);
+    dfree(h->dx);
+    dfree(h->r);
+    if (h->st_host) (void)hipHostFree(h->st_host);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    delete h;
+    return GSR_OK;
+}
+
+gsr_status gsr_get_size(const gsr_handle* h, int64_t* n_rows, int64_t* n_cols) {
+    if (!h) return fail(GSR_E_INVAL, "handle is NULL");
+    if (n_rows) *n_rows = h->g.m;
+    if (n_cols) *n_cols = h->g.n;
+    return GSR_OK;
+}
+
+gsr_status gsr_aprod1(gsr_handle* h, const double* x, double* y, void* stream) {
+    if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
+    GSR_TRY(set_device(h));
+    launch_aprod1<double, A1_ADD, false>(h, h->vals, x, nullptr, y, nullptr, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+gsr_status gsr_aprod2(gsr_handle* h, const double* y, double* x, void* stream) {
+    if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
+    GSR_TRY(set_device(h));
+    launch_aprod2<double, A2_ADD>(h, h->vals, y, x, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+gsr_status gsr_aprod1_f32v(gsr_handle* h, const double* x, double* y, void* stream) {
+    if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
+    if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
+    GSR_TRY(set_device(h));
+    launch_aprod1<float, A1_ADD, false>(h, h->vals32, x, nullptr, y, nullptr, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+gsr_status gsr_aprod2_f32v(gsr_handle* h, const double* y, double* x, void* stream) {
+    if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
+    if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
+    GSR_TRY(set_device(h));
+    launch_aprod2<float, A2_ADD>(h, h->vals32, y, x, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+gsr_status gsr_precond(gsr_handle* h, int32_t precision, double* p, void* stream) {
+    if (!h || !p) return fail(GSR_E_INVAL, "null argument");
+    const double* src = precision == GSR_F32V ? h->p32 : h->p64;
+    if (!src) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
+    GSR_TRY(set_device(h));
+    HIP_TRY(hipMemcpyAsync(p, src, sizeof(double) * h->g.n, hipMemcpyDeviceToDevice,
+                           as_stream(stream)));
+    return GSR_OK;
+}
+
+gsr_status gsr_residual(gsr_handle* h, const double* b, const double* x, double* r,
+                        void* stream) {
+    if (!h || !b || !x || !r) return fail(GSR_E_INVAL, "null argument");
+    GSR_TRY(set_device(h));
+    launch_aprod1<double, A1_RESID, false>(h, h->vals, x, nullptr, r, b, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_solve_opts* opts,
+                          gsr_solve_info* info, void* stream) {
+    g_last_error.clear();
+    if (!h || !x || (!b && h->g.m > 0)) return fail(GSR_E_INVAL, "null argument");
+    const gsr_solve_opts o = opts ? *opts : default_opts();
+    GSR_TRY(check_opts(o));
+    GSR_TRY(set_device(h));
+    hipStream_t s = as_stream(stream);
+    if (o.precision == GSR_F64)
+        return fwd_solve<double>(h, h->fwd64, h->vals, h->p64, b, x, o, info, s);
+
+    // binary32 coefficients inside, binary64 residual correction outside
+    if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
+    const Geo& g = h->g;
+    if (!h->dx) GSR_TRY(dalloc(&h->dx, g.n));
+    if (!h->r) GSR_TRY(dalloc(&h->r, g.m));
+    HIP_TRY(hipMemcpyAsync(h->r, b, sizeof(double) * g.m, hipMemcpyDeviceToDevice, s));
+    fill(x, g.n, 0.0, s);
+    int total_itn = 0, k = 0;
+    gsr_solve_info inner = {};
+    double* part = nullptr;
+    GSR_TRY(dalloc(&part, 2 * (size_t)h->Gn));
+    double sums[2] = {0, 0};
+    double* hp = nullptr;
+    hipError_t e = hipHostMalloc((void**)&hp, 2 * sizeof(double) * h->Gn, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        dfree(part);
+        return hip_fail(e, "hipHostMalloc");
+    }
+    gsr_status rc = GSR_OK;
+    while (k < o.max_refine) {
+        rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->p32, h->r, h->dx, o, &inner, s);
+        if (rc != GSR_OK) break;
+        total_itn += inner.itn;
+        ++k;
+        hipLaunchKernelGGL(k_axpy_norms, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->dx, x, part);
+        e = hipMemcpyAsync(hp, part, 2 * sizeof(double) * h->Gn, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "refinement norms");
+            break;
+        }
+        sums[0] = sums[1] = 0.0;
+        for (int q = 0; q < h->Gn; ++q) {
+            sums[0] += hp[q];
+            sums[1] += hp[h->Gn + q];
+        }
+        if (std::sqrt(sums[0]) <= o.refine_tol * std::sqrt(sums[1])) break;
+        if (k < o.max_refine)
+            launch_aprod1<double, A1_RESID, false>(h, h->vals, x, nullptr, h->r, b, s);
+    }
+    dfree(part);
+    (void)hipHostFree(hp);
+    if (rc != GSR_OK) return rc;
+    if (info) {
+        *info = inner;
+        info->itn = total_itn;
+        info->n_refine = k;
+    }
+    return GSR_OK;
+}
+
+gsr_status gsr_lsqr_solve_adjoint(gsr_handle* h, const double* gvec, double* mu, double* lam,
+                                  const gsr_solve_opts* opts, gsr_solve_info* info,
+                                  void* stream) {
+    g_last_error.clear();
+    if (!h || !gvec || !mu || !lam) return fail(GSR_E_INVAL, "null argument");
+    gsr_solve_opts o = opts ? *opts : default_opts();
+    GSR_TRY(check_opts(o));
+    if (o.precision != GSR_F64) return fail(GSR_E_UNSUPPORTED, "adjoint solve is binary64 only");
+    GSR_TRY(set_device(h));
+    hipStream_t s = as_stream(stream);
+    GSR_TRY(trans_solve(h, gvec, mu, o, info ? &info[0] : nullptr, s));
+    return fwd_solve<double>(h, h->fwd64, h->vals, h->p64, mu, lam, o, info ? &info[1] : nullptr,
+                             s);
+}
+
+gsr_status gsr_grad_vals(gsr_handle* h, const double* r, const double* mu, const double* x,
+                         const double* lam, double* dvals, void* stream) {
+    if (!h || !r || !mu || !x || !lam || !dvals) return fail(GSR_E_INVAL, "null argument");
+    if ((uintptr_t)dvals & 15) return fail(GSR_E_INVAL, "dvals must be 16-byte aligned");
+    GSR_TRY(set_device(h));
+    hipLaunchKernelGGL(k_grad_vals, dim3(h->G1), dim3(kBlock), 0, as_stream(stream), h->g,
+                       h->star, h->att, h->instr, r, mu, x, lam, dvals);
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,734 @@
+// Device kernels of the PC-LSQR hot path (arXiv 2212.11675) for gfx950.
+//
+// Matrix layout (Section 3): row i holds 24 coefficients in the slot order
+// [5 astrometric | 3 axes x 4 attitude | 6 instrumental | 1 global]; star[i] selects the
+// astrometric block, att[i] the start of the 4-wide block of every attitude axis (axis
+// stride n_dfa), instr[6i..6i+5] the instrumental columns.  All sums are binary64; the
+// coefficients are read as binary64 or from a binary32 copy (VT = float).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kPar = 24;     // coefficients per row
+constexpr int kAstro = 5;    // astrometric unknowns per star
+constexpr int kAxes = 3;     // attitude axes
+constexpr int kParAxis = 4;  // attitude coefficients per axis
+constexpr int kInstr = 6;    // instrumental coefficients per row
+constexpr int kWave = 64;    // gfx950 wavefront
+constexpr int kBlock = 256;  // threads per block of the row kernels
+constexpr int kInstrLdsMax = 10240;  // instrumental columns privatized in LDS (80 KiB)
+
+// Column geometry of one system.
+struct Geo {
+    int64_t m;     // rows
+    int64_t n;     // columns
+    int64_t att0;  // first attitude column  = 5 n_stars
+    int64_t ins0;  // first instrumental col = att0 + 3 n_dfa
+    int64_t glb0;  // global column          = ins0 + n_instr
+    int64_t n_stars;
+    int32_t T;     // n_dfa
+    int32_t I;     // n_instr
+};
+
+// Scalars of one LSQR recurrence, resident in device memory for the whole solve.
+// The vectors are stored unnormalized: u = su * u~, v = sv * v~.
+struct LsqrState {
+    double alpha, beta;   // current alpha_i, beta_i
+    double su, sv;        // 1/beta, 1/alpha (0 when the norm is 0)
+    double rhobar, phibar;
+    double f1, f2;        // pending update z += f1 w; w = sv v~ - f2 w
+    double fb;            // extra z += fb w after an exact beta = 0 breakdown
+    double anorm2, bnorm, rnorm, arnorm, znorm2;
+    double atol, btol;
+    int32_t itn, itnlim, fixed, istop, stop, pending, pend_b, nonfinite;
+};
+
+// ---------------------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over a block of NT threads; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NT / kWave; ++k) r += sh[k];
+    }
+    return r;
+}
+
+__device__ __forceinline__ void atomic_add_f64(double* p, double v) {
+    unsafeAtomicAdd(p, v);  // global_atomic_add_f64 (no CAS loop)
+}
+
+// The 24 coefficients of row i, widened to binary64.
+template <typename VT>
+__device__ __forceinline__ void load_row(const VT* __restrict__ vals, int64_t i, double a[kPar]);
+
+template <>
+__device__ __forceinline__ void load_row<double>(const double* __restrict__ vals, int64_t i,
+                                                 double a[kPar]) {
+    const f64x2* r = reinterpret_cast<const f64x2*>(vals + i * kPar);
+#pragma unroll
+    for (int k = 0; k < kPar / 2; ++k) {
+        const f64x2 t = __builtin_nontemporal_load(r + k);
+        a[2 * k] = t.x;
+        a[2 * k + 1] = t.y;
+    }
+}
+
+template <>
+__device__ __forceinline__ void load_row<float>(const float* __restrict__ vals, int64_t i,
+                                                double a[kPar]) {
+    const f32x4* r = reinterpret_cast<const f32x4*>(vals + i * kPar);
+#pragma unroll
+    for (int k = 0; k < kPar / 4; ++k) {
+        const f32x4 t = __builtin_nontemporal_load(r + k);
+        a[4 * k] = t.x;
+        a[4 * k + 1] = t.y;
+        a[4 * k + 2] = t.z;
+        a[4 * k + 3] = t.w;
+    }
+}
+
+__device__ __forceinline__ void load_instr(const int32_t* __restrict__ instr, int64_t i,
+                                           int32_t c[kInstr]) {
+    const i32x2* r = reinterpret_cast<const i32x2*>(instr + i * kInstr);
+#pragma unroll
+    for (int k = 0; k < kInstr / 2; ++k) {
+        const i32x2 t = __builtin_nontemporal_load(r + k);
+        c[2 * k] = t.x;
+        c[2 * k + 1] = t.y;
+    }
+}
+
+// Gather of x at the 24 columns of a row, times p (PRE) -- the sum of aprod 1.
+template <bool PRE>
+__device__ __forceinline__ double row_dot(const Geo& g, const double a[kPar], int32_t s, int32_t t,
+                                          const int32_t c[kInstr], const double* __restrict__ x,
+                                          const double* __restrict__ p) {
+    double sum = 0.0;
+    const int64_t ca = (int64_t)kAstro * s;
+#pragma unroll
+    for (int j = 0; j < kAstro; ++j) {
+        const double xv = PRE ? x[ca + j] * p[ca + j] : x[ca + j];
+        sum = fma(a[j], xv, sum);
+    }
+#pragma unroll
+    for (int ax = 0; ax < kAxes; ++ax) {
+        const int64_t cb = g.att0 + (int64_t)ax * g.T + t;
+#pragma unroll
+        for (int j = 0; j < kParAxis; ++j) {
+            const double xv = PRE ? x[cb + j] * p[cb + j] : x[cb + j];
+            sum = fma(a[kAstro + ax * kParAxis + j], xv, sum);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kInstr; ++j) {
+        const int64_t cc = g.ins0 + c[j];
+        const double xv = PRE ? x[cc] * p[cc] : x[cc];
+        sum = fma(a[17 + j], xv, sum);
+    }
+    {
+        const double xv = PRE ? x[g.glb0] * p[g.glb0] : x[g.glb0];
+        sum = fma(a[23], xv, sum);
+    }
+    return sum;
+}
+
+// ---------------------------------------------------------------------------------------
+// aprod 1:  sum_i = sum_k A[i,k] xx[col(i,k)]  with xx = x (PRE: x o p), then
+//   A1_ADD   : y[i] += sum_i
+//   A1_LSQR  : y[i] = xs * sum_i - ys * y[i]        (LSQR's  beta u = A v - alpha u)
+//              with (xs, ys) = (sv, alpha su) or, for the transposed operator,
+//              (su, beta sv); block partial of sum y[i]^2
+//   A1_RESID : y[i] = b[i] - sum_i
+enum { A1_ADD = 0, A1_LSQR = 1, A1_LSQR_T = 2, A1_RESID = 3 };
+
+template <typename VT, int MODE, bool PRE>
+static __global__ __launch_bounds__(kBlock) void k_aprod1(Geo g, const VT* __restrict__ vals,
+                                                   const int32_t* __restrict__ star,
+                                                   const int32_t* __restrict__ att,
+                                                   const int32_t* __restrict__ instr,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ p,
+                                                   double* __restrict__ y,
+                                                   const double* __restrict__ b,
+                                                   const LsqrState* __restrict__ st,
+                                                   double* __restrict__ partials) {
+    __shared__ double sh[kBlock / kWave];
+    double xs = 1.0, ys = 0.0;
+    if (MODE == A1_LSQR || MODE == A1_LSQR_T) {
+        if (st->stop) return;
+        if (MODE == A1_LSQR) {
+            xs = st->sv;
+            ys = st->alpha * st->su;
+        } else {
+            xs = st->su;
+            ys = st->beta * st->sv;
+        }
+    }
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < g.m; i += stride) {
+        double a[kPar];
+        int32_t c[kInstr];
+        load_row<VT>(vals, i, a);
+        load_instr(instr, i, c);
+        const int32_t s = __builtin_nontemporal_load(star + i);
+        const int32_t t = __builtin_nontemporal_load(att + i);
+        const double sum = row_dot<PRE>(g, a, s, t, c, x, p);
+        if (MODE == A1_ADD) {
+            y[i] += sum;
+        } else if (MODE == A1_RESID) {
+            y[i] = b[i] - sum;
+        } else {
+            const double u = (ys != 0.0) ? xs * sum - ys * y[i] : xs * sum;
+            y[i] = u;
+            acc = fma(u, u, acc);
+        }
+    }
+    if (MODE == A1_LSQR || MODE == A1_LSQR_T) {
+        const double tot = block_sum<kBlock>(acc, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// aprod 2:  x[col(i,k)] += A[i,k] yy_i  with
+//   A2_ADD  : yy_i = y[i]
+//   A2_LSQR : yy_i = su y[i]      (forward operator: y holds u~)
+//   A2_LSQR_T: yy_i = sv y[i]     (transposed operator: y holds v~)
+//   A2_SQ   : contribution A[i,k]^2 (column sums of squares for the preconditioner)
+// Astrometric columns: rows are sorted by star, so each wave reduces its 64 rows with a
+// segmented scan keyed by star and issues one atomic per (star segment, column).
+// Instrumental and global columns: accumulated in LDS for the whole block (all rows the
+// block visits), flushed with one atomic per column at the end.
+// Attitude columns: one device atomic per coefficient.
+enum { A2_ADD = 0, A2_LSQR = 1, A2_LSQR_T = 2, A2_SQ = 3 };
+
+template <typename VT, int MODE>
+static __global__ __launch_bounds__(kBlock) void k_aprod2(Geo g, const VT* __restrict__ vals,
+                                                   const int32_t* __restrict__ star,
+                                                   const int32_t* __restrict__ att,
+                                                   const int32_t* __restrict__ instr,
+                                                   const double* __restrict__ y,
+                                                   double* __restrict__ x,
+                                                   const LsqrState* __restrict__ st,
+                                                   int lds_instr) {
+    extern __shared__ double lds[];  // [I] instrumental (if lds_instr) then [1] global
+    double ysc = 1.0;
+    if (MODE == A2_LSQR || MODE == A2_LSQR_T) {
+        if (st->stop) return;
+        ysc = (MODE == A2_LSQR) ? st->su : st->sv;
+    }
+    const int nI = lds_instr ? g.I : 0;
+    double* lglob = lds + nI;
+    for (int k = threadIdx.x; k <= nI; k += kBlock) lds[k] = 0.0;
+    __syncthreads();
+
+    const int lane = threadIdx.x % kWave;
+    const int64_t ntiles = (g.m + kBlock - 1) / kBlock;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t i = tile * kBlock + threadIdx.x;
+        const bool valid = i < g.m;
+        double a[kPar];
+        int32_t c[kInstr];
+        int32_t s = -1, t = 0;
+        double yi = 0.0;
+        if (valid) {
+            load_row<VT>(vals, i, a);
+            load_instr(instr, i, c);
+            s = __builtin_nontemporal_load(star + i);
+            t = __builtin_nontemporal_load(att + i);
+            yi = (MODE == A2_SQ) ? 0.0 : ysc * y[i];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPar; ++k) a[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kInstr; ++k) c[k] = 0;
+        }
+        double v[kPar];
+#pragma unroll
+        for (int k = 0; k < kPar; ++k) v[k] = (MODE == A2_SQ) ? a[k] * a[k] : a[k] * yi;
+
+        // astrometric: segmented inclusive scan over the wave, keyed by star
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t ks = __shfl_up(s, off, kWave);
+            double o[kAstro];
+#pragma unroll
+            for (int j = 0; j < kAstro; ++j) o[j] = __shfl_up(v[j], off, kWave);
+            if (lane >= off && ks == s) {
+#pragma unroll
+                for (int j = 0; j < kAstro; ++j) v[j] += o[j];
+            }
+        }
+        const int32_t snext = __shfl_down(s, 1, kWave);
+        const bool seg_end = (lane == kWave - 1) || (snext != s);
+        if (valid && seg_end) {
+            const int64_t ca = (int64_t)kAstro * s;
+#pragma unroll
+            for (int j = 0; j < kAstro; ++j) atomic_add_f64(x + ca + j, v[j]);
+        }
+        if (valid) {
+            // attitude
+#pragma unroll
+            for (int ax = 0; ax < kAxes; ++ax) {
+                const int64_t cb = g.att0 + (int64_t)ax * g.T + t;
+#pragma unroll
+                for (int j = 0; j < kParAxis; ++j)
+                    atomic_add_f64(x + cb + j, v[kAstro + ax * kParAxis + j]);
+            }
+            // instrumental
+            if (lds_instr) {
+#pragma unroll
+                for (int j = 0; j < kInstr; ++j) atomicAdd(lds + c[j], v[17 + j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < kInstr; ++j) atomic_add_f64(x + g.ins0 + c[j], v[17 + j]);
+            }
+        }
+        // global: wave sum, one LDS atomic per wave
+        const double gs = wave_sum(valid ? v[23] : 0.0);
+        if (lane == 0) atomicAdd(lglob, gs);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nI; k += kBlock) {
+        const double val = lds[k];
+        if (val != 0.0) atomic_add_f64(x + g.ins0 + k, val);
+    }
+    if (threadIdx.x == 0 && *lglob != 0.0) atomic_add_f64(x + g.glb0, *lglob);
+}
+
+// ---------------------------------------------------------------------------------------
+// vectors
+
+static __global__ void k_fill(double* __restrict__ v, int64_t n, double val) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+        v[j] = val;
+}
+
+// p_j = 1/sqrt(ss_j) (0 for an empty column); ss is reset to 0; counts empty columns.
+static __global__ void k_recip_sqrt(int64_t n, double* __restrict__ ss, double* __restrict__ p,
+                             unsigned long long* __restrict__ n_empty) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long cnt = 0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const double s = ss[j];
+        ss[j] = 0.0;
+        p[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        cnt += (s > 0.0) ? 0 : 1;
+    }
+    if (cnt) atomicAdd(n_empty, cnt);
+}
+
+// u = src (o p if PRE); block partial of sum u^2.
+template <bool PRE>
+static __global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const double* __restrict__ src,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ u,
+                                                      double* __restrict__ partials) {
+    __shared__ double sh[kBlock / kWave];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+        const double v = PRE ? src[j] * p[j] : src[j];
+        u[j] = v;
+        acc = fma(v, v, acc);
+    }
+    const double tot = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Forward operator, after aprod 2 accumulated s = A^T (su u~):
+//   INIT : v~ = p o s;                 z = 0, w = 0
+//   else : apply the pending update  z += f1 w; w = sv v~ - f2 w  (old v~), then
+//          v~ = p o s - beta sv v~
+// s is reset to 0.  Partials (4 rows of G): sum v~^2, sum z^2, sum z w, sum w^2.
+template <bool INIT>
+static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __restrict__ s,
+                                                  const double* __restrict__ p,
+                                                  double* __restrict__ v, double* __restrict__ w,
+                                                  double* __restrict__ z,
+                                                  const LsqrState* __restrict__ st,
+                                                  double* __restrict__ partials) {
+    __shared__ double sh[kBlock / kWave];
+    if (!INIT && st->stop) return;
+    const bool pending = !INIT && st->pending;
+    const double f1 = st->f1, f2 = st->f2, sv = st->sv;
+    const double c1 = INIT ? 0.0 : st->beta * st->sv;
+    double avv = 0.0, azz = 0.0, azw = 0.0, aww = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+        const double sj = s[j];
+        s[j] = 0.0;
+        double vn;
+        if (INIT) {
+            vn = p[j] * sj;
+            z[j] = 0.0;
+            w[j] = 0.0;
+        } else {
+            const double vj = v[j];
+            if (pending) {
+                const double wj = w[j];
+                const double zj = fma(f1, wj, z[j]);
+                const double wn = sv * vj - f2 * wj;
+                z[j] = zj;
+                w[j] = wn;
+                azz = fma(zj, zj, azz);
+                azw = fma(zj, wn, azw);
+                aww = fma(wn, wn, aww);
+            }
+            vn = p[j] * sj - c1 * vj;
+        }
+        v[j] = vn;
+        avv = fma(vn, vn, avv);
+    }
+    const int G = gridDim.x;
+    double tot = block_sum<kBlock>(avv, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (!INIT) {
+        tot = block_sum<kBlock>(azz, sh);
+        if (threadIdx.x == 0) partials[G + blockIdx.x] = tot;
+        tot = block_sum<kBlock>(azw, sh);
+        if (threadIdx.x == 0) partials[2 * G + blockIdx.x] = tot;
+        tot = block_sum<kBlock>(aww, sh);
+        if (threadIdx.x == 0) partials[3 * G + blockIdx.x] = tot;
+    }
+}
+
+// Transposed operator, u-step after aprod 2 accumulated s = A^T (sv v~):
+//   u~ = p o s - alpha su u~ ; s = 0 ; partial sum u~^2.
+static __global__ __launch_bounds__(kBlock) void k_vec_tu(int64_t n, double* __restrict__ s,
+                                                   const double* __restrict__ p,
+                                                   double* __restrict__ u,
+                                                   const LsqrState* __restrict__ st,
+                                                   double* __restrict__ partials) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->stop) return;
+    const double c1 = st->alpha * st->su;
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+        const double sj = s[j];
+        s[j] = 0.0;
+        const double un = p[j] * sj - c1 * u[j];
+        u[j] = un;
+        acc = fma(un, un, acc);
+    }
+    const double tot = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Transposed operator: pending update in the (row-space) unknowns before v~ is replaced:
+//   z += f1 w; w = sv v~ - f2 w.  Partials (3 rows of G): sum z^2, sum z w, sum w^2.
+static __global__ __launch_bounds__(kBlock) void k_vec_zw(int64_t n, const double* __restrict__ v,
+                                                   double* __restrict__ w,
+                                                   double* __restrict__ z,
+                                                   const LsqrState* __restrict__ st,
+                                                   double* __restrict__ partials) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->stop) return;
+    const bool pending = st->pending;
+    const double f1 = st->f1, f2 = st->f2, sv = st->sv;
+    double azz = 0.0, azw = 0.0, aww = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    if (pending) {
+        for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+            const double wj = w[j];
+            const double zj = fma(f1, wj, z[j]);
+            const double wn = sv * v[j] - f2 * wj;
+            z[j] = zj;
+            w[j] = wn;
+            azz = fma(zj, zj, azz);
+            azw = fma(zj, wn, azw);
+            aww = fma(wn, wn, aww);
+        }
+    }
+    const int G = gridDim.x;
+    double tot = block_sum<kBlock>(azz, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    tot = block_sum<kBlock>(azw, sh);
+    if (threadIdx.x == 0) partials[G + blockIdx.x] = tot;
+    tot = block_sum<kBlock>(aww, sh);
+    if (threadIdx.x == 0) partials[2 * G + blockIdx.x] = tot;
+}
+
+// End of a solve: apply the pending updates, out = p o z (PRE) or z.
+template <bool PRE>
+static __global__ void k_final(int64_t n, const double* __restrict__ p, double* __restrict__ z,
+                        double* __restrict__ w, const double* __restrict__ v,
+                        double* __restrict__ out, const LsqrState* __restrict__ st) {
+    const bool pending = st->pending, pend_b = st->pend_b;
+    const double f1 = st->f1, f2 = st->f2, sv = st->sv, fb = st->fb;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        double zj = z[j];
+        if (pending) {
+            const double wj = w[j];
+            zj = fma(f1, wj, zj);
+            const double wn = sv * v[j] - f2 * wj;
+            if (pend_b) zj = fma(fb, wn, zj);
+            w[j] = wn;
+        }
+        z[j] = zj;
+        out[j] = PRE ? p[j] * zj : zj;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// scalar steps (one block of kBlock threads)
+
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int G,
+                                                  double* sh) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < G; k += kBlock) acc += part[k];
+    return block_sum<kBlock>(acc, sh);  // thread 0
+}
+
+// beta_1 = ||b||, u = b / beta_1.
+static __global__ __launch_bounds__(kBlock) void k_scal_init1(LsqrState* st, const double* part, int G,
+                                                       int32_t itnlim, int32_t fixed,
+                                                       double atol, double btol) {
+    __shared__ double sh[kBlock / kWave];
+    const double ss = reduce_partials(part, G, sh);
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(ss);
+    LsqrState s = {};
+    s.itnlim = itnlim;
+    s.fixed = fixed;
+    s.atol = atol;
+    s.btol = btol;
+    s.beta = beta;
+    s.bnorm = beta;
+    s.phibar = beta;
+    s.rnorm = beta;
+    s.su = beta > 0.0 ? 1.0 / beta : 0.0;
+    s.nonfinite = !isfinite(beta);
+    if (!(beta > 0.0)) {
+        s.istop = 4;
+        s.stop = 1;
+    }
+    *st = s;
+}
+
+// alpha_1 = ||v~||, v = v~ / alpha_1, w_1 = v_1 (applied by the first vector step).
+static __global__ __launch_bounds__(kBlock) void k_scal_init2(LsqrState* st, const double* part, int G) {
+    __shared__ double sh[kBlock / kWave];
+    const double ss = reduce_partials(part, G, sh);
+    if (threadIdx.x != 0) return;
+    if (st->stop) return;
+    const double alpha = sqrt(ss);
+    st->alpha = alpha;
+    st->sv = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    st->rhobar = alpha;
+    st->arnorm = alpha * st->beta;
+    st->f1 = 0.0;
+    st->f2 = 0.0;
+    st->pending = 1;  // w_1 = sv v~_1, z_0 = 0
+    if (!isfinite(alpha)) st->nonfinite = 1;
+    if (!(alpha > 0.0)) {
+        st->istop = 3;
+        st->stop = 1;
+        st->pending = 0;
+    } else if (st->itnlim <= 0) {
+        st->stop = 1;
+    }
+}
+
+// After the u-step: beta_{i+1} = ||u~||.  beta = 0 is an exact breakdown: the last Givens
+// step is taken here and the iteration stops.
+static __global__ __launch_bounds__(kBlock) void k_scal_beta(LsqrState* st, const double* part, int G) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->stop) return;
+    const double ss = reduce_partials(part, G, sh);
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(ss);
+    const double alpha = st->alpha;
+    st->anorm2 += alpha * alpha + beta * beta;
+    st->beta = beta;
+    if (!isfinite(beta)) {
+        st->nonfinite = 1;
+        st->stop = 1;
+        return;
+    }
+    if (beta > 0.0) {
+        st->su = 1.0 / beta;
+        return;
+    }
+    // beta = 0: rho = |rhobar|, c = rhobar / rho, s = 0
+    const double rhobar = st->rhobar;
+    const double rho = sqrt(rhobar * rhobar);
+    const double c = rhobar / rho;
+    const double phi = c * st->phibar;
+    st->fb = phi / rho;
+    st->pend_b = 1;
+    st->rhobar = -c * alpha;
+    st->phibar = 0.0;
+    st->itn += 1;
+    st->rnorm = 0.0;
+    st->arnorm = 0.0;
+    st->istop = 3;
+    st->stop = 1;
+}
+
+// After the v-step: alpha_{i+1} = ||v~||, Givens rotation, stopping tests.
+// pz: partial sums of z_{i-1}^2, z_{i-1} w_i, w_i^2 (rows of Gz), to update ||z_i||.
+static __global__ __launch_bounds__(kBlock) void k_scal_alpha(LsqrState* st, const double* pv, int Gv,
+                                                       const double* pz, int Gz) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->stop) return;
+    const double vv = reduce_partials(pv, Gv, sh);
+    const double zz = reduce_partials(pz, Gz, sh);
+    const double zw = reduce_partials(pz + Gz, Gz, sh);
+    const double ww = reduce_partials(pz + 2 * Gz, Gz, sh);
+    if (threadIdx.x != 0) return;
+    const double alpha = sqrt(vv);
+    const double beta = st->beta;
+    const double rhobar = st->rhobar, phibar = st->phibar;
+    const double rho = sqrt(rhobar * rhobar + beta * beta);
+    const double c = rhobar / rho, s = beta / rho;
+    const double theta = s * alpha;
+    const double phi = c * phibar;
+    st->rhobar = -c * alpha;
+    st->phibar = s * phibar;
+    st->f1 = phi / rho;
+    st->f2 = theta / rho;
+    st->pending = 1;
+    st->alpha = alpha;
+    st->sv = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    st->itn += 1;
+    st->rnorm = st->phibar;
+    st->arnorm = st->phibar * alpha * fabs(c);
+    const double f1 = st->f1;
+    st->znorm2 = fmax(zz + 2.0 * f1 * zw + f1 * f1 * ww, 0.0);
+    if (!isfinite(alpha) || !isfinite(st->znorm2)) {
+        st->nonfinite = 1;
+        st->stop = 1;
+        return;
+    }
+    const double anorm = sqrt(st->anorm2);
+    const double znorm = sqrt(st->znorm2);
+    if (!(alpha > 0.0)) {
+        st->istop = 3;
+        st->stop = 1;
+    } else if (!st->fixed &&
+               st->rnorm <= st->btol * st->bnorm + st->atol * anorm * znorm) {
+        st->istop = 1;
+        st->stop = 1;
+    } else if (!st->fixed && st->arnorm <= st->atol * anorm * st->rnorm) {
+        st->istop = 2;
+        st->stop = 1;
+    }
+    if (st->itn >= st->itnlim) st->stop = 1;
+}
+
+// ---------------------------------------------------------------------------------------
+// precision form and gradient
+
+static __global__ void k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+        dst[j] = (float)src[j];  // round to nearest even
+}
+
+// x += d; partials (2 rows of G): sum d^2, sum x^2
+static __global__ __launch_bounds__(kBlock) void k_axpy_norms(int64_t n, const double* __restrict__ d,
+                                                       double* __restrict__ x,
+                                                       double* __restrict__ partials) {
+    __shared__ double sh[kBlock / kWave];
+    double add = 0.0, axx = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+        const double dj = d[j];
+        const double xj = x[j] + dj;
+        x[j] = xj;
+        add = fma(dj, dj, add);
+        axx = fma(xj, xj, axx);
+    }
+    double tot = block_sum<kBlock>(add, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    tot = block_sum<kBlock>(axx, sh);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = tot;
+}
+
+// dvals[i, k] = r_i lam_c - mu_i x_c  on the stored pattern.
+static __global__ __launch_bounds__(kBlock) void k_grad_vals(Geo g, const int32_t* __restrict__ star,
+                                                      const int32_t* __restrict__ att,
+                                                      const int32_t* __restrict__ instr,
+                                                      const double* __restrict__ r,
+                                                      const double* __restrict__ mu,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ dvals) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < g.m; i += stride) {
+        int32_t c[kInstr];
+        load_instr(instr, i, c);
+        const int32_t s = star[i], t = att[i];
+        const double ri = r[i], mi = mu[i];
+        double o[kPar];
+        const int64_t ca = (int64_t)kAstro * s;
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) o[j] = ri * lam[ca + j] - mi * x[ca + j];
+#pragma unroll
+        for (int ax = 0; ax < kAxes; ++ax) {
+            const int64_t cb = g.att0 + (int64_t)ax * g.T + t;
+#pragma unroll
+            for (int j = 0; j < kParAxis; ++j)
+                o[kAstro + ax * kParAxis + j] = ri * lam[cb + j] - mi * x[cb + j];
+        }
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) {
+            const int64_t cc = g.ins0 + c[j];
+            o[17 + j] = ri * lam[cc] - mi * x[cc];
+        }
+        o[23] = ri * lam[g.glb0] - mi * x[g.glb0];
+        f64x2* dst = reinterpret_cast<f64x2*>(dvals + i * kPar);
+#pragma unroll
+        for (int k = 0; k < kPar / 2; ++k) dst[k] = f64x2{o[2 * k], o[2 * k + 1]};
+    }
+}
+
+// Index checks: bit 0 star out of range, bit 1 stars not sorted, bit 2 attitude start out
+// of range, bit 3 instrumental index out of range.
+static __global__ void k_validate(Geo g, const int32_t* __restrict__ star,
+                           const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
+                           int* __restrict__ flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.m; i += stride) {
+        const int32_t s = star[i];
+        if (s < 0 || s >= g.n_stars) bad |= 1;
+        if (i > 0 && star[i - 1] > s) bad |= 2;
+        const int32_t t = att[i];
+        if (t < 0 || t > g.T - kParAxis) bad |= 4;
+        for (int j = 0; j < kInstr; ++j) {
+            const int32_t c = instr[i * kInstr + j];
+            if (c < 0 || c >= g.I) bad |= 8;
+        }
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+}  // namespace gsr
