@@ -17,6 +17,9 @@
 #include "gsr.h"
 #include "gsr_internal.hpp"
 #include "kernels.hpp"
+#include "products.hpp"
+
+#include <hipcub/hipcub.hpp>
 
 using namespace gsr;
 
@@ -119,12 +122,19 @@ struct gsr_handle {
     float* vals32 = nullptr;
     double *p64 = nullptr, *p32 = nullptr;
     double* s = nullptr;       // [n] aprod 2 accumulator (kept zero between uses)
+    double* xt = nullptr;      // [n] operand of the next aprod 1 (p o v)
+    // attitude coefficients in attitude-start order (built at setup)
+    int32_t *rowT = nullptr, *tT = nullptr;
+    double* attT64 = nullptr;
+    float* attT32 = nullptr;
+    double* part_ig = nullptr;  // [G2s][n_instr + 1] block sums of the star-ordered pass
     double *partA = nullptr, *partB = nullptr;
     LsqrState* st = nullptr;   // device scalars
     LsqrState* st_host = nullptr;  // pinned mirror
-    int G1 = 1, G2 = 1, Gn = 1, Gm = 1;
-    int lds_instr = 0;
-    size_t lds2 = 0;
+    int G1 = 1, G2s = 1, G2t = 1, Gn = 1, Gm = 1;
+    int chunk1 = 16, chunk2s = 16, chunk2t = 16;
+    int lds1 = 0, lds2 = 0;           // instrumental columns staged / privatized in LDS
+    size_t lds1_bytes = 0, lds2_bytes = 0;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
     double *dx = nullptr, *r = nullptr;  // refinement
     hipStream_t cap = nullptr;     // capture stream
@@ -133,7 +143,6 @@ struct gsr_handle {
 namespace {
 
 constexpr int kVecBlocksMax = 2048;
-constexpr int kRowBlocksMax = 8192;
 constexpr int kGraphIters = 16;
 
 template <typename T>
@@ -181,35 +190,89 @@ void fill(double* v, int64_t n, double val, hipStream_t s) {
 
 // ---- launches of the products --------------------------------------------------------
 
-template <typename VT, int MODE, bool PRE>
-void launch_aprod1(const gsr_handle* h, const VT* vals, const double* x, const double* p,
-                   double* y, const double* b, hipStream_t s) {
-    hipLaunchKernelGGL((k_aprod1<VT, MODE, PRE>), dim3(h->G1), dim3(kBlock), 0, s, h->g, vals,
-                       h->star, h->att, h->instr, x, p, y, b, h->st, h->partA);
+constexpr int kBlock1 = 512;   // aprod 1
+constexpr int kBlock2s = 512;  // aprod 2, star-ordered pass
+constexpr int kBlock2t = 256;  // aprod 2, attitude pass
+
+// y (op)= A xx
+template <typename VT, int MODE>
+void launch_aprod1(const gsr_handle* h, const VT* vals, const double* xx, double* y,
+                   const double* b, hipStream_t s) {
+    hipLaunchKernelGGL((k_aprod1<VT, MODE>), dim3(h->G1), dim3(kBlock1), h->lds1_bytes, s, h->g,
+                       vals, h->star, h->att, h->instr, xx, y, b, h->st, h->partA, h->chunk1,
+                       h->lds1);
 }
 
+// x += A^T y: star-ordered pass (astrometric, instrumental, global), reduction of the
+// instrumental/global block sums, attitude pass over the t-ordered copy.
 template <typename VT, int MODE>
-void launch_aprod2(const gsr_handle* h, const VT* vals, const double* y, double* x,
-                   hipStream_t s) {
-    hipLaunchKernelGGL((k_aprod2<VT, MODE>), dim3(h->G2), dim3(kBlock), h->lds2, s, h->g, vals,
-                       h->star, h->att, h->instr, y, x, h->st, h->lds_instr);
+void launch_aprod2(const gsr_handle* h, const VT* vals, const VT* attT, const double* y,
+                   double* x, hipStream_t s) {
+    const Geo& g = h->g;
+    hipLaunchKernelGGL((k_aprod2_star<VT, MODE>), dim3(h->G2s), dim3(kBlock2s), h->lds2_bytes, s,
+                       g, vals, h->star, h->instr, y, x, h->st, h->part_ig, h->chunk2s, h->lds2);
+    if (h->lds2) {
+        const int ncols = g.I + 1;
+        hipLaunchKernelGGL(k_reduce_partials, dim3((ncols + 255) / 256), dim3(256), 0, s, ncols,
+                           h->G2s, h->part_ig, x + g.ins0, h->st,
+                           (int)(MODE == A2_LSQR || MODE == A2_LSQR_T));
+    }
+    hipLaunchKernelGGL((k_aprod2_att<VT, MODE>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
+                       h->rowT, h->tT, y, x, h->st, h->chunk2t);
 }
 
 // p = 1 / column norms of `vals`.  Synchronizes.
 template <typename VT>
-gsr_status colnorm(gsr_handle* h, const VT* vals, double* p, hipStream_t s,
+gsr_status colnorm(gsr_handle* h, const VT* vals, const VT* attT, double* p, hipStream_t s,
                    unsigned long long* n_empty) {
     unsigned long long* d_cnt = nullptr;
     GSR_TRY(dalloc(&d_cnt, 1));
     HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(*d_cnt), s));
     fill(h->s, h->g.n, 0.0, s);
-    launch_aprod2<VT, A2_SQ>(h, vals, nullptr, h->s, s);
+    launch_aprod2<VT, A2_SQ>(h, vals, attT, nullptr, h->s, s);
     hipLaunchKernelGGL(k_recip_sqrt, dim3(grid_for(h->g.n, kBlock, kVecBlocksMax)), dim3(kBlock),
                        0, s, h->g.n, h->s, p, d_cnt);
     hipError_t e = hipMemcpyAsync(n_empty, d_cnt, sizeof(*d_cnt), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dfree(d_cnt);
     if (e != hipSuccess) return hip_fail(e, "column norms");
+    return GSR_OK;
+}
+
+// Rows sorted by attitude start t (stable radix sort of (t, row)) and the attitude
+// coefficients gathered in that order: the attitude pass of aprod 2 then sees every column's
+// contributions as consecutive runs.  Synchronizes.
+gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
+    const Geo& g = h->g;
+    const int64_t m = g.m;
+    GSR_TRY(dalloc(&h->rowT, m));
+    GSR_TRY(dalloc(&h->tT, m));
+    GSR_TRY(dalloc(&h->attT64, m * kAxes * kParAxis));
+    if (m == 0) return GSR_OK;
+    if (m > (int64_t)INT32_MAX) return fail(GSR_E_UNSUPPORTED, "more than 2^31-1 rows");
+    int32_t* iota = nullptr;
+    GSR_TRY(dalloc(&iota, m));
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(m, kBlock, kVecBlocksMax)), dim3(kBlock), 0, s, m,
+                       iota);
+    int end_bit = 1;
+    while (end_bit < 31 && (1LL << end_bit) <= (int64_t)g.T) ++end_bit;
+    size_t temp_bytes = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, h->att, h->tT, iota,
+                                                      h->rowT, (int)m, 0, end_bit, s);
+    void* temp = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&temp, std::max<size_t>(temp_bytes, 1));
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, h->att, h->tT, iota, h->rowT,
+                                               (int)m, 0, end_bit, s);
+    if (e == hipSuccess) {
+        const int64_t total = m * kAxes * kParAxis;
+        hipLaunchKernelGGL(k_gather_att<double>, dim3(grid_for(total, kBlock, 8192)),
+                           dim3(kBlock), 0, s, m, h->vals, h->rowT, h->attT64);
+        e = hipStreamSynchronize(s);
+    }
+    dfree(temp);
+    dfree(iota);
+    if (e != hipSuccess) return hip_fail(e, "attitude ordering");
     return GSR_OK;
 }
 
@@ -225,20 +288,20 @@ void mark(hipEvent_t e, hipStream_t s) {
 }
 
 template <typename VT>
-void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const double* p,
-                   hipStream_t s, const IterEvents* ev = nullptr) {
+void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
+                   const double* p, hipStream_t s, const IterEvents* ev = nullptr) {
     const Geo& g = h->g;
-    // beta u = A (p o v) - alpha u
+    // beta u = A (p o v) - alpha u        (xt = p o v~ from the previous vector step)
     if (ev) mark(ev->a1_begin, s);
-    launch_aprod1<VT, A1_LSQR, true>(h, vals, w.v, p, w.u, nullptr, s);
+    launch_aprod1<VT, A1_LSQR>(h, vals, h->xt, w.u, nullptr, s);
     if (ev) mark(ev->a1_end, s);
     hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
     // alpha v = p o A^T u - beta v, with the pending z/w update of the previous iteration
     if (ev) mark(ev->a2_begin, s);
-    launch_aprod2<VT, A2_LSQR>(h, vals, w.u, h->s, s);
+    launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
     if (ev) mark(ev->a2_end, s);
     hipLaunchKernelGGL(k_vec_v<false>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
-                       w.z, h->st, h->partB);
+                       w.z, h->xt, h->st, h->partB);
     hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn,
                        h->partB + h->Gn, h->Gn);
 }
@@ -250,16 +313,16 @@ void trans_iteration(const gsr_handle* h, LsqrWork& w, hipStream_t s,
     const Geo& g = h->g;
     // beta u = D A^T v - alpha u
     if (ev) mark(ev->a2_begin, s);
-    launch_aprod2<double, A2_LSQR_T>(h, h->vals, w.v, h->s, s);
+    launch_aprod2<double, A2_LSQR_T>(h, h->vals, h->attT64, w.v, h->s, s);
     if (ev) mark(ev->a2_end, s);
-    hipLaunchKernelGGL(k_vec_tu, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, h->p64, w.u, h->st,
-                       h->partA);
+    hipLaunchKernelGGL(k_vec_tu, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, h->p64, w.u, h->xt,
+                       h->st, h->partA);
     hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn);
     // pending z/w update, then alpha v = A D u - beta v
     hipLaunchKernelGGL(k_vec_zw, dim3(h->Gm), dim3(kBlock), 0, s, g.m, w.v, w.w, w.z, h->st,
                        h->partB);
     if (ev) mark(ev->a1_begin, s);
-    launch_aprod1<double, A1_LSQR_T, true>(h, h->vals, w.u, h->p64, w.v, nullptr, s);
+    launch_aprod1<double, A1_LSQR_T>(h, h->vals, h->xt, w.v, nullptr, s);
     if (ev) mark(ev->a1_end, s);
     hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1,
                        h->partB, h->Gm);
@@ -385,28 +448,31 @@ gsr_status read_info(gsr_handle* h, gsr_solve_info* info, hipStream_t s,
 
 // PC-LSQR on A (binary64 or binary32 coefficients): x = p o z.  Synchronizes.
 template <typename VT>
-gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const double* p,
-                     const double* b, double* x, const gsr_solve_opts& o, gsr_solve_info* info,
-                     hipStream_t s) {
+gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
+                     const double* p, const double* b, double* x, const gsr_solve_opts& o,
+                     gsr_solve_info* info, hipStream_t s) {
     const Geo& g = h->g;
     GSR_TRY(ensure_work(w, g.m, g.n));
-    GSR_TRY(capture_graph(h, w, [&](hipStream_t cs) { fwd_iteration<VT>(h, w, vals, p, cs); }));
+    GSR_TRY(capture_graph(
+        h, w, [&](hipStream_t cs) { fwd_iteration<VT>(h, w, vals, attT, p, cs); }));
     // beta_1 u_1 = b
     hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
-                       w.u, h->partA);
+                       w.u, nullptr, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gm,
                        o.itnlim, o.fixed_iters, o.atol, o.btol);
     // alpha_1 v_1 = p o A^T u_1  (the initial aprod 2)
     fill(h->s, g.n, 0.0, s);
-    launch_aprod2<VT, A2_LSQR>(h, vals, w.u, h->s, s);
+    launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
     hipLaunchKernelGGL(k_vec_v<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
-                       w.z, h->st, h->partB);
+                       w.z, h->xt, h->st, h->partB);
     hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
     ProfileOut prof;
     if (o.profile)
         GSR_TRY(run_profiled(
             h, o, s,
-            [&](hipStream_t cs, const IterEvents* ev) { fwd_iteration<VT>(h, w, vals, p, cs, ev); },
+            [&](hipStream_t cs, const IterEvents* ev) {
+                fwd_iteration<VT>(h, w, vals, attT, p, cs, ev);
+            },
             &prof.ms1, &prof.ms2, &prof.n));
     else
         GSR_TRY(run_iterations(h, w, o, s));
@@ -424,11 +490,11 @@ gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_
     GSR_TRY(capture_graph(h, w, [&](hipStream_t cs) { trans_iteration(h, w, cs); }));
     // beta_1 u_1 = D g
     hipLaunchKernelGGL(k_copy_norm<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, gvec, h->p64,
-                       w.u, h->partA);
+                       w.u, h->xt, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn,
                        o.itnlim, o.fixed_iters, o.atol, o.btol);
     // alpha_1 v_1 = A D u_1
-    launch_aprod1<double, A1_LSQR_T, true>(h, h->vals, w.u, h->p64, w.v, nullptr, s);
+    launch_aprod1<double, A1_LSQR_T>(h, h->vals, h->xt, w.v, nullptr, s);
     fill(w.w, g.m, 0.0, s);
     fill(w.z, g.m, 0.0, s);
     hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
@@ -529,28 +595,55 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         return st;
     };
 
-    h->G1 = grid_for(g.m, kBlock, kRowBlocksMax);
+    // launch shapes: persistent grids sized by occupancy; row chunks of 16..1024 rows
+    // so that every wave slot of the GPU gets several chunks
     h->Gn = grid_for(g.n, kBlock, kVecBlocksMax);
     h->Gm = grid_for(g.m, kBlock, kVecBlocksMax);
-    h->lds_instr = g.I <= kInstrLdsMax;
-    h->lds2 = sizeof(double) * ((h->lds_instr ? g.I : 0) + 1);
+    h->lds1 = g.I <= kInstrLdsMax;
+    h->lds2 = g.I <= kInstrLdsMax;
+    h->lds1_bytes = h->lds1 ? sizeof(double) * g.I : 0;
+    h->lds2_bytes = h->lds2 ? sizeof(double) * (g.I + 1) : 0;
     {
-        int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_aprod2<double, A2_LSQR>, kBlock, h->lds2);
-        if (e != hipSuccess || per_cu < 1) per_cu = 1;
-        const int64_t tiles = (g.m + kBlock - 1) / kBlock;
-        h->G2 = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)per_cu * n_cu));
+        auto occ = [&](const void* fn, int threads, size_t lds) {
+            int per_cu = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+            return (e != hipSuccess || per_cu < 1) ? 1 : per_cu;
+        };
+        auto chunk_for = [&](int waves) {
+            int64_t c = g.m / (4 * (int64_t)std::max(waves, 1));
+            c = std::max<int64_t>(kStepRows, std::min<int64_t>(1024, c));
+            return (int)((c + kStepRows - 1) / kStepRows * kStepRows);
+        };
+        auto grid = [&](int per_cu, int threads, int chunk) {
+            const int64_t chunks = (g.m + chunk - 1) / chunk;
+            const int64_t need = (chunks + threads / kWave - 1) / (threads / kWave);
+            return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * n_cu));
+        };
+        const int o1 = occ((const void*)k_aprod1<double, A1_LSQR>, kBlock1, h->lds1_bytes);
+        const int o2s = occ((const void*)k_aprod2_star<double, A2_LSQR>, kBlock2s, h->lds2_bytes);
+        const int o2t = occ((const void*)k_aprod2_att<double, A2_LSQR>, kBlock2t, 0);
+        h->chunk1 = chunk_for(o1 * n_cu * kBlock1 / kWave);
+        h->chunk2s = chunk_for(o2s * n_cu * kBlock2s / kWave);
+        h->chunk2t = chunk_for(o2t * n_cu * kBlock2t / kWave);
+        h->G1 = grid(o1, kBlock1, h->chunk1);
+        h->G2s = grid(o2s, kBlock2s, h->chunk2s);
+        h->G2t = grid(o2t, kBlock2t, h->chunk2t);
     }
     gsr_status st;
     if ((st = dalloc(&h->p64, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->s, g.n)) != GSR_OK) return bail(st);
+    if ((st = dalloc(&h->xt, g.n)) != GSR_OK) return bail(st);
     const int part_len = std::max(std::max(h->G1, h->Gm), h->Gn);
     if ((st = dalloc(&h->partA, part_len)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->partB, 4 * (size_t)part_len)) != GSR_OK) return bail(st);
+    if (h->lds2 &&
+        (st = dalloc(&h->part_ig, (size_t)h->G2s * (g.I + 1))) != GSR_OK)
+        return bail(st);
     if ((st = dalloc(&h->st, 1)) != GSR_OK) return bail(st);
     {
-        hipError_t e = hipHostMalloc((void**)&h->st_host, sizeof(LsqrState), hipHostMallocDefault);
+        hipError_t e = hipMemsetAsync(h->st, 0, sizeof(LsqrState), s);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+        e = hipHostMalloc((void**)&h->st_host, sizeof(LsqrState), hipHostMallocDefault);
         if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
         e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
@@ -576,17 +669,24 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
                              (flags & 4) ? " attitude start out of [0, n_dfa-4]" : "",
                              (flags & 8) ? " instrumental index out of range" : ""));
     }
+    if ((st = build_att_order(h, s)) != GSR_OK) return bail(st);
     unsigned long long n_empty = 0;
-    if ((st = colnorm<double>(h, vals, h->p64, s, &n_empty)) != GSR_OK) return bail(st);
+    if ((st = colnorm<double>(h, vals, h->attT64, h->p64, s, &n_empty)) != GSR_OK)
+        return bail(st);
     if (n_empty && !so.allow_empty_cols)
         return bail(fail(GSR_E_LAYOUT, "%llu all-zero column(s); set allow_empty_cols", n_empty));
     if (so.build_f32) {
-        if ((st = dalloc(&h->vals32, (size_t)g.m * kPar)) != GSR_OK) return bail(st);
+        const int64_t nnz = (int64_t)g.m * kPar, natt = (int64_t)g.m * kAxes * kParAxis;
+        if ((st = dalloc(&h->vals32, nnz)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->attT32, natt)) != GSR_OK) return bail(st);
         if ((st = dalloc(&h->p32, g.n)) != GSR_OK) return bail(st);
-        hipLaunchKernelGGL(k_to_f32, dim3(grid_for((int64_t)g.m * kPar, kBlock, 8192)),
-                           dim3(kBlock), 0, s, (int64_t)g.m * kPar, vals, h->vals32);
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s, nnz,
+                           vals, h->vals32);
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(natt, kBlock, 8192)), dim3(kBlock), 0, s,
+                           natt, h->attT64, h->attT32);
         unsigned long long n_empty32 = 0;
-        if ((st = colnorm<float>(h, h->vals32, h->p32, s, &n_empty32)) != GSR_OK) return bail(st);
+        if ((st = colnorm<float>(h, h->vals32, h->attT32, h->p32, s, &n_empty32)) != GSR_OK)
+            return bail(st);
     }
     *out = h;
     return GSR_OK;
@@ -601,6 +701,12 @@ gsr_status gsr_destroy(gsr_handle* h) {
     free_work(h->fwd32);
     free_work(h->trans);
     dfree(h->vals32);
+    dfree(h->attT32);
+    dfree(h->attT64);
+    dfree(h->rowT);
+    dfree(h->tT);
+    dfree(h->xt);
+    dfree(h->part_ig);
     dfree(h->p64);
     dfree(h->p32);
     dfree(h->s);
@@ -625,7 +731,7 @@ gsr_status gsr_get_size(const gsr_handle* h, int64_t* n_rows, int64_t* n_cols) {
 gsr_status gsr_aprod1(gsr_handle* h, const double* x, double* y, void* stream) {
     if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
     GSR_TRY(set_device(h));
-    launch_aprod1<double, A1_ADD, false>(h, h->vals, x, nullptr, y, nullptr, as_stream(stream));
+    launch_aprod1<double, A1_ADD>(h, h->vals, x, y, nullptr, as_stream(stream));
     HIP_TRY(hipGetLastError());
     return GSR_OK;
 }
@@ -633,7 +739,7 @@ gsr_status gsr_aprod1(gsr_handle* h, const double* x, double* y, void* stream) {
 gsr_status gsr_aprod2(gsr_handle* h, const double* y, double* x, void* stream) {
     if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
     GSR_TRY(set_device(h));
-    launch_aprod2<double, A2_ADD>(h, h->vals, y, x, as_stream(stream));
+    launch_aprod2<double, A2_ADD>(h, h->vals, h->attT64, y, x, as_stream(stream));
     HIP_TRY(hipGetLastError());
     return GSR_OK;
 }
@@ -642,7 +748,7 @@ gsr_status gsr_aprod1_f32v(gsr_handle* h, const double* x, double* y, void* stre
     if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
     if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
     GSR_TRY(set_device(h));
-    launch_aprod1<float, A1_ADD, false>(h, h->vals32, x, nullptr, y, nullptr, as_stream(stream));
+    launch_aprod1<float, A1_ADD>(h, h->vals32, x, y, nullptr, as_stream(stream));
     HIP_TRY(hipGetLastError());
     return GSR_OK;
 }
@@ -651,7 +757,7 @@ gsr_status gsr_aprod2_f32v(gsr_handle* h, const double* y, double* x, void* stre
     if (!h || !x || !y) return fail(GSR_E_INVAL, "null argument");
     if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
     GSR_TRY(set_device(h));
-    launch_aprod2<float, A2_ADD>(h, h->vals32, y, x, as_stream(stream));
+    launch_aprod2<float, A2_ADD>(h, h->vals32, h->attT32, y, x, as_stream(stream));
     HIP_TRY(hipGetLastError());
     return GSR_OK;
 }
@@ -670,7 +776,7 @@ gsr_status gsr_residual(gsr_handle* h, const double* b, const double* x, double*
                         void* stream) {
     if (!h || !b || !x || !r) return fail(GSR_E_INVAL, "null argument");
     GSR_TRY(set_device(h));
-    launch_aprod1<double, A1_RESID, false>(h, h->vals, x, nullptr, r, b, as_stream(stream));
+    launch_aprod1<double, A1_RESID>(h, h->vals, x, r, b, as_stream(stream));
     HIP_TRY(hipGetLastError());
     return GSR_OK;
 }
@@ -684,7 +790,7 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
     GSR_TRY(set_device(h));
     hipStream_t s = as_stream(stream);
     if (o.precision == GSR_F64)
-        return fwd_solve<double>(h, h->fwd64, h->vals, h->p64, b, x, o, info, s);
+        return fwd_solve<double>(h, h->fwd64, h->vals, h->attT64, h->p64, b, x, o, info, s);
 
     // binary32 coefficients inside, binary64 residual correction outside
     if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
@@ -706,7 +812,8 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
     }
     gsr_status rc = GSR_OK;
     while (k < o.max_refine) {
-        rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->p32, h->r, h->dx, o, &inner, s);
+        rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx, o, &inner,
+                              s);
         if (rc != GSR_OK) break;
         total_itn += inner.itn;
         ++k;
@@ -724,7 +831,7 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
         }
         if (std::sqrt(sums[0]) <= o.refine_tol * std::sqrt(sums[1])) break;
         if (k < o.max_refine)
-            launch_aprod1<double, A1_RESID, false>(h, h->vals, x, nullptr, h->r, b, s);
+            launch_aprod1<double, A1_RESID>(h, h->vals, x, h->r, b, s);
     }
     dfree(part);
     (void)hipHostFree(hp);
@@ -748,7 +855,8 @@ gsr_status gsr_lsqr_solve_adjoint(gsr_handle* h, const double* gvec, double* mu,
     GSR_TRY(set_device(h));
     hipStream_t s = as_stream(stream);
     GSR_TRY(trans_solve(h, gvec, mu, o, info ? &info[0] : nullptr, s));
-    return fwd_solve<double>(h, h->fwd64, h->vals, h->p64, mu, lam, o, info ? &info[1] : nullptr,
+    return fwd_solve<double>(h, h->fwd64, h->vals, h->attT64, h->p64, mu, lam, o,
+                             info ? &info[1] : nullptr,
                              s);
 }
 

@@ -79,36 +79,6 @@ __device__ __forceinline__ void atomic_add_f64(double* p, double v) {
     unsafeAtomicAdd(p, v);  // global_atomic_add_f64 (no CAS loop)
 }
 
-// The 24 coefficients of row i, widened to binary64.
-template <typename VT>
-__device__ __forceinline__ void load_row(const VT* __restrict__ vals, int64_t i, double a[kPar]);
-
-template <>
-__device__ __forceinline__ void load_row<double>(const double* __restrict__ vals, int64_t i,
-                                                 double a[kPar]) {
-    const f64x2* r = reinterpret_cast<const f64x2*>(vals + i * kPar);
-#pragma unroll
-    for (int k = 0; k < kPar / 2; ++k) {
-        const f64x2 t = __builtin_nontemporal_load(r + k);
-        a[2 * k] = t.x;
-        a[2 * k + 1] = t.y;
-    }
-}
-
-template <>
-__device__ __forceinline__ void load_row<float>(const float* __restrict__ vals, int64_t i,
-                                                double a[kPar]) {
-    const f32x4* r = reinterpret_cast<const f32x4*>(vals + i * kPar);
-#pragma unroll
-    for (int k = 0; k < kPar / 4; ++k) {
-        const f32x4 t = __builtin_nontemporal_load(r + k);
-        a[4 * k] = t.x;
-        a[4 * k + 1] = t.y;
-        a[4 * k + 2] = t.z;
-        a[4 * k + 3] = t.w;
-    }
-}
-
 __device__ __forceinline__ void load_instr(const int32_t* __restrict__ instr, int64_t i,
                                            int32_t c[kInstr]) {
     const i32x2* r = reinterpret_cast<const i32x2*>(instr + i * kInstr);
@@ -118,205 +88,6 @@ __device__ __forceinline__ void load_instr(const int32_t* __restrict__ instr, in
         c[2 * k] = t.x;
         c[2 * k + 1] = t.y;
     }
-}
-
-// Gather of x at the 24 columns of a row, times p (PRE) -- the sum of aprod 1.
-template <bool PRE>
-__device__ __forceinline__ double row_dot(const Geo& g, const double a[kPar], int32_t s, int32_t t,
-                                          const int32_t c[kInstr], const double* __restrict__ x,
-                                          const double* __restrict__ p) {
-    double sum = 0.0;
-    const int64_t ca = (int64_t)kAstro * s;
-#pragma unroll
-    for (int j = 0; j < kAstro; ++j) {
-        const double xv = PRE ? x[ca + j] * p[ca + j] : x[ca + j];
-        sum = fma(a[j], xv, sum);
-    }
-#pragma unroll
-    for (int ax = 0; ax < kAxes; ++ax) {
-        const int64_t cb = g.att0 + (int64_t)ax * g.T + t;
-#pragma unroll
-        for (int j = 0; j < kParAxis; ++j) {
-            const double xv = PRE ? x[cb + j] * p[cb + j] : x[cb + j];
-            sum = fma(a[kAstro + ax * kParAxis + j], xv, sum);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kInstr; ++j) {
-        const int64_t cc = g.ins0 + c[j];
-        const double xv = PRE ? x[cc] * p[cc] : x[cc];
-        sum = fma(a[17 + j], xv, sum);
-    }
-    {
-        const double xv = PRE ? x[g.glb0] * p[g.glb0] : x[g.glb0];
-        sum = fma(a[23], xv, sum);
-    }
-    return sum;
-}
-
-// ---------------------------------------------------------------------------------------
-// aprod 1:  sum_i = sum_k A[i,k] xx[col(i,k)]  with xx = x (PRE: x o p), then
-//   A1_ADD   : y[i] += sum_i
-//   A1_LSQR  : y[i] = xs * sum_i - ys * y[i]        (LSQR's  beta u = A v - alpha u)
-//              with (xs, ys) = (sv, alpha su) or, for the transposed operator,
-//              (su, beta sv); block partial of sum y[i]^2
-//   A1_RESID : y[i] = b[i] - sum_i
-enum { A1_ADD = 0, A1_LSQR = 1, A1_LSQR_T = 2, A1_RESID = 3 };
-
-template <typename VT, int MODE, bool PRE>
-static __global__ __launch_bounds__(kBlock) void k_aprod1(Geo g, const VT* __restrict__ vals,
-                                                   const int32_t* __restrict__ star,
-                                                   const int32_t* __restrict__ att,
-                                                   const int32_t* __restrict__ instr,
-                                                   const double* __restrict__ x,
-                                                   const double* __restrict__ p,
-                                                   double* __restrict__ y,
-                                                   const double* __restrict__ b,
-                                                   const LsqrState* __restrict__ st,
-                                                   double* __restrict__ partials) {
-    __shared__ double sh[kBlock / kWave];
-    double xs = 1.0, ys = 0.0;
-    if (MODE == A1_LSQR || MODE == A1_LSQR_T) {
-        if (st->stop) return;
-        if (MODE == A1_LSQR) {
-            xs = st->sv;
-            ys = st->alpha * st->su;
-        } else {
-            xs = st->su;
-            ys = st->beta * st->sv;
-        }
-    }
-    double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < g.m; i += stride) {
-        double a[kPar];
-        int32_t c[kInstr];
-        load_row<VT>(vals, i, a);
-        load_instr(instr, i, c);
-        const int32_t s = __builtin_nontemporal_load(star + i);
-        const int32_t t = __builtin_nontemporal_load(att + i);
-        const double sum = row_dot<PRE>(g, a, s, t, c, x, p);
-        if (MODE == A1_ADD) {
-            y[i] += sum;
-        } else if (MODE == A1_RESID) {
-            y[i] = b[i] - sum;
-        } else {
-            const double u = (ys != 0.0) ? xs * sum - ys * y[i] : xs * sum;
-            y[i] = u;
-            acc = fma(u, u, acc);
-        }
-    }
-    if (MODE == A1_LSQR || MODE == A1_LSQR_T) {
-        const double tot = block_sum<kBlock>(acc, sh);
-        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// aprod 2:  x[col(i,k)] += A[i,k] yy_i  with
-//   A2_ADD  : yy_i = y[i]
-//   A2_LSQR : yy_i = su y[i]      (forward operator: y holds u~)
-//   A2_LSQR_T: yy_i = sv y[i]     (transposed operator: y holds v~)
-//   A2_SQ   : contribution A[i,k]^2 (column sums of squares for the preconditioner)
-// Astrometric columns: rows are sorted by star, so each wave reduces its 64 rows with a
-// segmented scan keyed by star and issues one atomic per (star segment, column).
-// Instrumental and global columns: accumulated in LDS for the whole block (all rows the
-// block visits), flushed with one atomic per column at the end.
-// Attitude columns: one device atomic per coefficient.
-enum { A2_ADD = 0, A2_LSQR = 1, A2_LSQR_T = 2, A2_SQ = 3 };
-
-template <typename VT, int MODE>
-static __global__ __launch_bounds__(kBlock) void k_aprod2(Geo g, const VT* __restrict__ vals,
-                                                   const int32_t* __restrict__ star,
-                                                   const int32_t* __restrict__ att,
-                                                   const int32_t* __restrict__ instr,
-                                                   const double* __restrict__ y,
-                                                   double* __restrict__ x,
-                                                   const LsqrState* __restrict__ st,
-                                                   int lds_instr) {
-    extern __shared__ double lds[];  // [I] instrumental (if lds_instr) then [1] global
-    double ysc = 1.0;
-    if (MODE == A2_LSQR || MODE == A2_LSQR_T) {
-        if (st->stop) return;
-        ysc = (MODE == A2_LSQR) ? st->su : st->sv;
-    }
-    const int nI = lds_instr ? g.I : 0;
-    double* lglob = lds + nI;
-    for (int k = threadIdx.x; k <= nI; k += kBlock) lds[k] = 0.0;
-    __syncthreads();
-
-    const int lane = threadIdx.x % kWave;
-    const int64_t ntiles = (g.m + kBlock - 1) / kBlock;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t i = tile * kBlock + threadIdx.x;
-        const bool valid = i < g.m;
-        double a[kPar];
-        int32_t c[kInstr];
-        int32_t s = -1, t = 0;
-        double yi = 0.0;
-        if (valid) {
-            load_row<VT>(vals, i, a);
-            load_instr(instr, i, c);
-            s = __builtin_nontemporal_load(star + i);
-            t = __builtin_nontemporal_load(att + i);
-            yi = (MODE == A2_SQ) ? 0.0 : ysc * y[i];
-        } else {
-#pragma unroll
-            for (int k = 0; k < kPar; ++k) a[k] = 0.0;
-#pragma unroll
-            for (int k = 0; k < kInstr; ++k) c[k] = 0;
-        }
-        double v[kPar];
-#pragma unroll
-        for (int k = 0; k < kPar; ++k) v[k] = (MODE == A2_SQ) ? a[k] * a[k] : a[k] * yi;
-
-        // astrometric: segmented inclusive scan over the wave, keyed by star
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int32_t ks = __shfl_up(s, off, kWave);
-            double o[kAstro];
-#pragma unroll
-            for (int j = 0; j < kAstro; ++j) o[j] = __shfl_up(v[j], off, kWave);
-            if (lane >= off && ks == s) {
-#pragma unroll
-                for (int j = 0; j < kAstro; ++j) v[j] += o[j];
-            }
-        }
-        const int32_t snext = __shfl_down(s, 1, kWave);
-        const bool seg_end = (lane == kWave - 1) || (snext != s);
-        if (valid && seg_end) {
-            const int64_t ca = (int64_t)kAstro * s;
-#pragma unroll
-            for (int j = 0; j < kAstro; ++j) atomic_add_f64(x + ca + j, v[j]);
-        }
-        if (valid) {
-            // attitude
-#pragma unroll
-            for (int ax = 0; ax < kAxes; ++ax) {
-                const int64_t cb = g.att0 + (int64_t)ax * g.T + t;
-#pragma unroll
-                for (int j = 0; j < kParAxis; ++j)
-                    atomic_add_f64(x + cb + j, v[kAstro + ax * kParAxis + j]);
-            }
-            // instrumental
-            if (lds_instr) {
-#pragma unroll
-                for (int j = 0; j < kInstr; ++j) atomicAdd(lds + c[j], v[17 + j]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < kInstr; ++j) atomic_add_f64(x + g.ins0 + c[j], v[17 + j]);
-            }
-        }
-        // global: wave sum, one LDS atomic per wave
-        const double gs = wave_sum(valid ? v[23] : 0.0);
-        if (lane == 0) atomicAdd(lglob, gs);
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nI; k += kBlock) {
-        const double val = lds[k];
-        if (val != 0.0) atomic_add_f64(x + g.ins0 + k, val);
-    }
-    if (threadIdx.x == 0 && *lglob != 0.0) atomic_add_f64(x + g.glb0, *lglob);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -342,11 +113,13 @@ static __global__ void k_recip_sqrt(int64_t n, double* __restrict__ ss, double* 
     if (cnt) atomicAdd(n_empty, cnt);
 }
 
-// u = src (o p if PRE); block partial of sum u^2.
+// u = src (o p if PRE); block partial of sum u^2
+// (PRE: also xt = p o u, the operand of the next aprod 1)
 template <bool PRE>
 static __global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const double* __restrict__ src,
                                                       const double* __restrict__ p,
                                                       double* __restrict__ u,
+                                                      double* __restrict__ xt,
                                                       double* __restrict__ partials) {
     __shared__ double sh[kBlock / kWave];
     double acc = 0.0;
@@ -354,6 +127,7 @@ static __global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const do
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
         const double v = PRE ? src[j] * p[j] : src[j];
         u[j] = v;
+        if (PRE) xt[j] = p[j] * v;
         acc = fma(v, v, acc);
     }
     const double tot = block_sum<kBlock>(acc, sh);
@@ -364,12 +138,13 @@ static __global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const do
 //   INIT : v~ = p o s;                 z = 0, w = 0
 //   else : apply the pending update  z += f1 w; w = sv v~ - f2 w  (old v~), then
 //          v~ = p o s - beta sv v~
-// s is reset to 0.  Partials (4 rows of G): sum v~^2, sum z^2, sum z w, sum w^2.
+// s is reset to 0 and xt = p o v~ (the operand of the next aprod 1) is written.
+// Partials (4 rows of G): sum v~^2, sum z^2, sum z w, sum w^2.
 template <bool INIT>
 static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __restrict__ s,
                                                   const double* __restrict__ p,
                                                   double* __restrict__ v, double* __restrict__ w,
-                                                  double* __restrict__ z,
+                                                  double* __restrict__ z, double* __restrict__ xt,
                                                   const LsqrState* __restrict__ st,
                                                   double* __restrict__ partials) {
     __shared__ double sh[kBlock / kWave];
@@ -402,6 +177,7 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
             vn = p[j] * sj - c1 * vj;
         }
         v[j] = vn;
+        xt[j] = p[j] * vn;
         avv = fma(vn, vn, avv);
     }
     const int G = gridDim.x;
@@ -418,10 +194,10 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
 }
 
 // Transposed operator, u-step after aprod 2 accumulated s = A^T (sv v~):
-//   u~ = p o s - alpha su u~ ; s = 0 ; partial sum u~^2.
+//   u~ = p o s - alpha su u~ ; s = 0 ; xt = p o u~ ; partial sum u~^2.
 static __global__ __launch_bounds__(kBlock) void k_vec_tu(int64_t n, double* __restrict__ s,
                                                    const double* __restrict__ p,
-                                                   double* __restrict__ u,
+                                                   double* __restrict__ u, double* __restrict__ xt,
                                                    const LsqrState* __restrict__ st,
                                                    double* __restrict__ partials) {
     __shared__ double sh[kBlock / kWave];
@@ -434,6 +210,7 @@ static __global__ __launch_bounds__(kBlock) void k_vec_tu(int64_t n, double* __r
         s[j] = 0.0;
         const double un = p[j] * sj - c1 * u[j];
         u[j] = un;
+        xt[j] = p[j] * un;
         acc = fma(un, un, acc);
     }
     const double tot = block_sum<kBlock>(acc, sh);
@@ -506,13 +283,11 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
     return block_sum<kBlock>(acc, sh);  // thread 0
 }
 
+// The scalar recurrences of one LSQR instance (applied by one thread per instance).
+
 // beta_1 = ||b||, u = b / beta_1.
-static __global__ __launch_bounds__(kBlock) void k_scal_init1(LsqrState* st, const double* part, int G,
-                                                       int32_t itnlim, int32_t fixed,
-                                                       double atol, double btol) {
-    __shared__ double sh[kBlock / kWave];
-    const double ss = reduce_partials(part, G, sh);
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void scal_init1(LsqrState* st, double ss, int32_t itnlim, int32_t fixed,
+                                           double atol, double btol) {
     const double beta = sqrt(ss);
     LsqrState s = {};
     s.itnlim = itnlim;
@@ -533,10 +308,7 @@ static __global__ __launch_bounds__(kBlock) void k_scal_init1(LsqrState* st, con
 }
 
 // alpha_1 = ||v~||, v = v~ / alpha_1, w_1 = v_1 (applied by the first vector step).
-static __global__ __launch_bounds__(kBlock) void k_scal_init2(LsqrState* st, const double* part, int G) {
-    __shared__ double sh[kBlock / kWave];
-    const double ss = reduce_partials(part, G, sh);
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void scal_init2(LsqrState* st, double ss) {
     if (st->stop) return;
     const double alpha = sqrt(ss);
     st->alpha = alpha;
@@ -558,11 +330,8 @@ static __global__ __launch_bounds__(kBlock) void k_scal_init2(LsqrState* st, con
 
 // After the u-step: beta_{i+1} = ||u~||.  beta = 0 is an exact breakdown: the last Givens
 // step is taken here and the iteration stops.
-static __global__ __launch_bounds__(kBlock) void k_scal_beta(LsqrState* st, const double* part, int G) {
-    __shared__ double sh[kBlock / kWave];
+__device__ __forceinline__ void scal_beta(LsqrState* st, double ss) {
     if (st->stop) return;
-    const double ss = reduce_partials(part, G, sh);
-    if (threadIdx.x != 0) return;
     const double beta = sqrt(ss);
     const double alpha = st->alpha;
     st->anorm2 += alpha * alpha + beta * beta;
@@ -592,17 +361,11 @@ static __global__ __launch_bounds__(kBlock) void k_scal_beta(LsqrState* st, cons
     st->stop = 1;
 }
 
-// After the v-step: alpha_{i+1} = ||v~||, Givens rotation, stopping tests.
-// pz: partial sums of z_{i-1}^2, z_{i-1} w_i, w_i^2 (rows of Gz), to update ||z_i||.
-static __global__ __launch_bounds__(kBlock) void k_scal_alpha(LsqrState* st, const double* pv, int Gv,
-                                                       const double* pz, int Gz) {
-    __shared__ double sh[kBlock / kWave];
+// After the v-step: alpha_{i+1} = ||v~||, Givens rotation, stopping tests.  zz, zw, ww are
+// sum z_{i-1}^2, sum z_{i-1} w_i, sum w_i^2, giving ||z_i||^2 without another pass.
+__device__ __forceinline__ void scal_alpha(LsqrState* st, double vv, double zz, double zw,
+                                           double ww) {
     if (st->stop) return;
-    const double vv = reduce_partials(pv, Gv, sh);
-    const double zz = reduce_partials(pz, Gz, sh);
-    const double zw = reduce_partials(pz + Gz, Gz, sh);
-    const double ww = reduce_partials(pz + 2 * Gz, Gz, sh);
-    if (threadIdx.x != 0) return;
     const double alpha = sqrt(vv);
     const double beta = st->beta;
     const double rhobar = st->rhobar, phibar = st->phibar;
@@ -641,6 +404,41 @@ static __global__ __launch_bounds__(kBlock) void k_scal_alpha(LsqrState* st, con
         st->stop = 1;
     }
     if (st->itn >= st->itnlim) st->stop = 1;
+}
+
+static __global__ __launch_bounds__(kBlock) void k_scal_init1(LsqrState* st, const double* part,
+                                                              int G, int32_t itnlim, int32_t fixed,
+                                                              double atol, double btol) {
+    __shared__ double sh[kBlock / kWave];
+    const double ss = reduce_partials(part, G, sh);
+    if (threadIdx.x == 0) scal_init1(st, ss, itnlim, fixed, atol, btol);
+}
+
+static __global__ __launch_bounds__(kBlock) void k_scal_init2(LsqrState* st, const double* part,
+                                                              int G) {
+    __shared__ double sh[kBlock / kWave];
+    const double ss = reduce_partials(part, G, sh);
+    if (threadIdx.x == 0) scal_init2(st, ss);
+}
+
+static __global__ __launch_bounds__(kBlock) void k_scal_beta(LsqrState* st, const double* part,
+                                                             int G) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->stop) return;
+    const double ss = reduce_partials(part, G, sh);
+    if (threadIdx.x == 0) scal_beta(st, ss);
+}
+
+// pz: partial sums of z_{i-1}^2, z_{i-1} w_i, w_i^2 (rows of Gz).
+static __global__ __launch_bounds__(kBlock) void k_scal_alpha(LsqrState* st, const double* pv,
+                                                              int Gv, const double* pz, int Gz) {
+    __shared__ double sh[kBlock / kWave];
+    if (st->stop) return;
+    const double vv = reduce_partials(pv, Gv, sh);
+    const double zz = reduce_partials(pz, Gz, sh);
+    const double zw = reduce_partials(pz + Gz, Gz, sh);
+    const double ww = reduce_partials(pz + 2 * Gz, Gz, sh);
+    if (threadIdx.x == 0) scal_alpha(st, vv, zz, zw, ww);
 }
 
 // ---------------------------------------------------------------------------------------
