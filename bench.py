@@ -35,6 +35,20 @@ def algorithmic_bytes(m: int, n: int, value_bytes: int = 8) -> dict:
     return {"aprod1": a1, "aprod2": a2}
 
 
+def pass_bytes(m: int, n: int, shape, fused: bool, value_bytes: int = 8) -> dict:
+    """Algorithmic bytes of the two timed passes of one iteration.
+    fused row pass: coefficients, index map, u read+write, xt once, s of the astrometric,
+    instrumental and global columns read+written; attitude pass: the attitude copy, its
+    row and t indices, u gathered once per row, s of the attitude columns read+written."""
+    if not fused:
+        ab = algorithmic_bytes(m, n, value_bytes)
+        return {"pass1": ab["aprod1"], "pass2": ab["aprod2"]}
+    n_att = 3 * shape.n_dfa
+    p1 = 24 * m * value_bytes + 32 * m + 16 * m + 8 * n + 16 * (n - n_att)
+    p2 = 12 * m * value_bytes + 8 * m + 8 * m + 16 * n_att
+    return {"pass1": p1, "pass2": p2}
+
+
 def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
     """The oracle (single-threaded C) on the same system: per-iteration time from the
     difference of two fixed-iteration solves (setup of p excluded)."""
@@ -54,6 +68,213 @@ def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
                       f"{t2 - t0:.1f} s of CPU work)"}
 
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def upload_system(shape, chunk_rows: int = 10_000_000):
+    """Generate `shape` on the host in row chunks and copy it to the GPU (bounded host
+    memory); returns the device arrays and the dims."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    dev = torch.device("cuda:0")
+    rp = shape.row_ptr()
+    m = int(rp[-1])
+    t = {"vals": torch.empty(24 * m, dtype=torch.float64, device=dev),
+         "star": torch.empty(m, dtype=torch.int32, device=dev),
+         "att": torch.empty(m, dtype=torch.int32, device=dev),
+         "instr": torch.empty(6 * m, dtype=torch.int32, device=dev)}
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        part = synth.rows(shape, r0, r1, row_ptr=rp)
+        t["vals"][24 * r0: 24 * r1].copy_(torch.from_numpy(part["vals"]))
+        t["star"][r0:r1].copy_(torch.from_numpy(part["star"]))
+        t["att"][r0:r1].copy_(torch.from_numpy(part["att"]))
+        t["instr"][6 * r0: 6 * r1].copy_(torch.from_numpy(part["instr"]))
+    torch.cuda.synchronize()
+    dims = dict(n_rows=m, n_stars=shape.n_stars, n_dfa=shape.n_dfa, n_instr=shape.n_instr)
+    return t, dims
+
+
+def form_precision(args) -> dict:
+    """binary64 PC-LSQR vs binary32-coefficient PC-LSQR with binary64 residual correction,
+    both taken to 1e-8 relative error against a converged binary64 reference."""
+    import torch
+
+    import synth
+    from paper_2212_11675_amd import gsr
+
+    shape = synth.WORKLOADS[args.workload]
+    t, d = upload_system(shape)
+    m, n = d["n_rows"], shape.n_cols
+    dev = torch.device("cuda:0")
+    h = gsr.gsr_lsqr_setup(gsr.make_dims(m, d["n_stars"], d["n_dfa"], d["n_instr"]), t["vals"],
+                           t["star"], t["att"], t["instr"], build_f32=True)
+    b = torch.from_numpy(synth.noise(shape)).to(dev)
+    gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
+    x_ref = torch.empty(n, dtype=torch.float64, device=dev)
+    ref = gsr.gsr_lsqr_solve(h, b, x_ref, gsr.solve_opts(itnlim=1000, fixed_iters=False,
+                                                         atol=1e-15, btol=1e-15))
+    log(f"reference: {ref['itn']} iterations, istop {ref['istop']}")
+    nref = torch.linalg.norm(x_ref)
+    x = torch.empty_like(x_ref)
+
+    def timed(opts):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = gsr.gsr_lsqr_solve(h, b, x, opts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, info, float(torch.linalg.norm(x - x_ref) / nref)
+
+    # binary64: fewest fixed iterations that reach 1e-8
+    k64, best64 = None, None
+    for k in range(5, 400, 1):
+        dt, info, err = timed(gsr.solve_opts(itnlim=k, fixed_iters=True))
+        if err <= 1e-8:
+            k64 = k
+            best64 = min(timed(gsr.solve_opts(itnlim=k, fixed_iters=True))[0] for _ in range(3))
+            break
+    log(f"binary64: {k64} iterations to 1e-8, {best64:.4f} s")
+    # binary32 coefficients + refinement: first inner solve to its floor, then short ones
+    pre = timed(gsr.solve_opts(itnlim=k64 + 20, fixed_iters=True, precision=gsr.GSR_F32V,
+                               max_refine=1))[2]
+    best32, cfg32 = None, None
+    for inner in range(max(3, k64 // 3), 2 * k64):
+        o = gsr.solve_opts(itnlim=inner, fixed_iters=True, precision=gsr.GSR_F32V,
+                           max_refine=2, refine_tol=0.0)
+        dt, info, err = timed(o)
+        if err <= 1e-8:
+            best32 = min(timed(o)[0] for _ in range(3))
+            cfg32 = {"inner_iterations": inner, "outer_steps": info["n_refine"],
+                     "total_iterations": info["itn"], "rel_err": err}
+            break
+    log(f"binary32+refinement: {cfg32}, {best32}")
+    h.close()
+    return {
+        "metric": "time to 1e-8 relative solution error (binary64 vs binary32-stored + refined)",
+        "value": round(best64 / best32, 4) if best32 else None,
+        "unit": "speedup (binary64 time / refined time)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64 / f32-stored",
+        "data": "synthetic",
+        "config": {"workload": shape.name, "rows": m, "cols": n},
+        "f64": {"iterations": k64, "seconds": best64},
+        "f32_refined": {"seconds": best32, **(cfg32 or {})},
+        "pre_refinement_rel_err": pre,
+        "reference_iterations": ref["itn"],
+    }
+
+
+def form_batch(args) -> dict:
+    """64 independent systems x 8 right-hand sides, one captured graph per solve."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2212_11675_amd import gsr
+
+    dev = torch.device("cuda:0")
+    shapes = synth.batch_shapes()
+    k = 8
+    parts = [synth.system(sh) for sh in shapes]
+    row_offset = np.concatenate([[0], np.cumsum([p["dims"]["n_rows"] for p in parts])])
+    dims = [gsr.make_dims(p["dims"]["n_rows"], sh.n_stars, sh.n_dfa, sh.n_instr)
+            for p, sh in zip(parts, shapes)]
+    cat = {key: torch.from_numpy(np.concatenate([p[key] for p in parts])).to(dev)
+           for key in ("vals", "star", "att", "instr")}
+    M = int(row_offset[-1])
+    t0 = time.perf_counter()
+    bt = gsr.gsr_batch_setup(dims, row_offset.tolist(), cat["vals"], cat["star"], cat["att"],
+                             cat["instr"], k, allow_empty_cols=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    # right-hand sides b_j = A x_j + e_j through the library's batched product
+    X = torch.empty((bt.n, k), dtype=torch.float64)
+    B = torch.empty((M, k), dtype=torch.float64)
+    for s, sh in enumerate(shapes):
+        for j in range(k):
+            X[bt.col_offset[s]:bt.col_offset[s + 1], j] = torch.from_numpy(synth.rhs_x(sh, j))
+            B[int(row_offset[s]):int(row_offset[s + 1]), j] = torch.from_numpy(
+                synth.rhs_noise(sh, j, int(row_offset[s + 1] - row_offset[s])))
+    Xd, Bd = X.reshape(-1).to(dev), B.reshape(-1).to(dev)
+    gsr.gsr_batch_aprod1(bt, Xd, Bd)
+    Xs = torch.empty_like(Xd)
+    opts = gsr.solve_opts(itnlim=args.iters, fixed_iters=True)
+    for _ in range(args.warmup):
+        gsr.gsr_batch_solve(bt, Bd, Xs, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gsr.gsr_batch_solve(bt, Bd, Xs, opts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    err = float(torch.linalg.norm(Xs - Xd) / torch.linalg.norm(Xd))
+    bt.close()
+    return {
+        "metric": "batched PC-LSQR: systems/s and per-system latency",
+        "value": round(len(shapes) / dt, 3),
+        "unit": "systems/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch64_k8_stars1e3to2e5_obs10to60", "systems": len(shapes),
+                   "rhs_per_system": k, "rows": M, "cols": bt.n,
+                   "iterations": args.iters, "setup_s": round(t_setup, 3)},
+        "latency_ms_per_solve": round(1e3 * dt, 3),
+        "pairs_per_s": round(len(shapes) * k / dt, 2),
+        "solution_rel_err_vs_x_true": err,
+    }
+
+
+def form_grad(args) -> dict:
+    """Forward (converged PC-LSQR) + backward (adjoint LSQR + coefficient gradient)."""
+    import torch
+
+    import synth
+    from paper_2212_11675_amd import autograd as gad
+
+    shape = synth.WORKLOADS[args.workload]
+    t, d = upload_system(shape)
+    dev = torch.device("cuda:0")
+    st = gad.Structure(t["star"], t["att"], t["instr"], shape.n_stars, shape.n_dfa,
+                       shape.n_instr)
+    from paper_2212_11675_amd import gsr
+    h = gsr.gsr_lsqr_setup(st.dims(), t["vals"], t["star"], t["att"], t["instr"])
+    b = torch.from_numpy(synth.noise(shape)).to(dev)
+    gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
+    h.close()
+    xr = torch.from_numpy(synth.x_ref(shape)).to(dev)
+
+    def step():
+        vals = t["vals"].requires_grad_(True)
+        bb = b.clone().requires_grad_(True)
+        x = gad.lstsq(vals, bb, st, itnlim=args.iters, atol=1e-12, btol=1e-12)
+        loss = ((x - xr) ** 2).sum()
+        loss.backward()
+        vals.grad = None
+        return float(loss)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {
+        "metric": "forward+backward through PC-LSQR (adjoint LSQR), seconds per step",
+        "value": round(dt, 4), "unit": "s/step", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": shape.name, "rows": d["n_rows"], "cols": shape.n_cols,
+                   "tolerance": 1e-12},
+        "loss": loss,
+    }
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,7 +282,11 @@ def main() -> None:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--workload", default="stars1e6_obs20_dfa3e4_instr6e3")
+    ap.add_argument("--form", default="f64", choices=["f64", "precision", "batch", "grad"],
+                    help="f64: the headline binary64 solve; the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--no-events", action="store_true",
                     help="replay the captured iteration graph instead of event-bracketed launches")
     args = ap.parse_args()
@@ -70,6 +295,20 @@ def main() -> None:
               "multi-GPU split of the path is a design note, not a measured configuration",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB (1073741824 B read + written each)")
+        del src, dst
+    if args.form != "f64":
+        fn = {"precision": form_precision, "batch": form_batch, "grad": form_grad}[args.form]
+        print(json.dumps(fn(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -122,22 +361,32 @@ def main() -> None:
     roofline = None
     extra = {}
     if not args.no_events:
-        ms1 = float(np.mean([i["ms_aprod1"] for i in infos]))
-        ms2 = float(np.mean([i["ms_aprod2"] for i in infos]))
-        ab = algorithmic_bytes(m, n)
-        gbps1 = ab["aprod1"] / (ms1 * 1e-3) / 1e9
-        gbps2 = ab["aprod2"] / (ms2 * 1e-3) / 1e9
-        dom = "aprod1" if ms1 >= ms2 else "aprod2"
-        gb, msd = (gbps1, ms1) if dom == "aprod1" else (gbps2, ms2)
+        ms1 = float(np.mean([i["ms_pass1"] for i in infos]))
+        ms2 = float(np.mean([i["ms_pass2"] for i in infos]))
+        fused = bool(infos[-1]["fused"])
+        pb = pass_bytes(m, n, shape, fused)
+        gbps1 = pb["pass1"] / (ms1 * 1e-3) / 1e9
+        gbps2 = pb["pass2"] / (ms2 * 1e-3) / 1e9
+        names = (("k_aprod12", "k_reduce_partials + k_aprod2_att") if fused
+                 else ("k_aprod1", "k_aprod2_star + k_reduce_partials + k_aprod2_att"))
+        dom = 0 if ms1 >= ms2 else 1
+        gb, msd = (gbps1, ms1) if dom == 0 else (gbps2, ms2)
         roofline = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBPS, 4), "traffic": None,
-                    "kernel": f"k_{dom}", "ms_per_launch": round(msd, 4),
-                    "algorithmic_bytes_per_launch": ab[dom]}
-        extra["aprod"] = {
-            "aprod1": {"ms": round(ms1, 4), "GBps": round(gbps1, 1),
-                       "frac_of_peak": round(gbps1 / HBM_PEAK_GBPS, 4)},
-            "aprod2": {"ms": round(ms2, 4), "GBps": round(gbps2, 1),
-                       "frac_of_peak": round(gbps2 / HBM_PEAK_GBPS, 4)},
+                    "kernel": names[dom], "ms_per_launch": round(msd, 4),
+                    "algorithmic_bytes_per_launch": pb["pass1" if dom == 0 else "pass2"]}
+        ab = algorithmic_bytes(m, n)
+        extra["passes"] = {
+            "fused_row_pass": fused,
+            "pass1": {"kernels": names[0], "ms": round(ms1, 4), "bytes": pb["pass1"],
+                      "GBps": round(gbps1, 1), "frac_of_peak": round(gbps1 / HBM_PEAK_GBPS, 4)},
+            "pass2": {"kernels": names[1], "ms": round(ms2, 4), "bytes": pb["pass2"],
+                      "GBps": round(gbps2, 1), "frac_of_peak": round(gbps2 / HBM_PEAK_GBPS, 4)},
+            # the two products as separate operations would move aprod1 + aprod2 bytes;
+            # the fused schedule reads each row once, so this can exceed the peak
+            "aprod1_plus_aprod2_bytes": ab["aprod1"] + ab["aprod2"],
+            "aprod1_plus_aprod2_equivalent_GBps": round(
+                (ab["aprod1"] + ab["aprod2"]) / ((ms1 + ms2) * 1e-3) / 1e9, 1),
         }
 
     cpu = None

@@ -103,10 +103,13 @@ typedef struct gsr_solve_info {
     double anorm;     /* Frobenius estimate of ||A D||                                      */
     double znorm;     /* ||z||, z = x / p the preconditioned unknowns                      */
     double bnorm;     /* ||b|| (of the last inner right-hand side)                         */
-    double ms_aprod1; /* profile = 1: mean duration of one aprod 1 launch in the iterations  */
-    double ms_aprod2; /* profile = 1: mean duration of one aprod 2 launch in the iterations  */
-    int32_t n_aprod1; /* number of launches averaged                                         */
-    int32_t n_aprod2;
+    double ms_pass1;  /* profile = 1: mean duration per iteration of the row-ordered pass
+                         (aprod 1, fused with the star-ordered part of aprod 2 when the
+                         instrumental columns fit in LDS)                                   */
+    double ms_pass2;  /* profile = 1: mean duration per iteration of the rest of aprod 2
+                         (block-sum reduction and attitude pass; all of aprod 2 if unfused) */
+    int32_t n_pass;   /* number of iterations averaged                                      */
+    int32_t fused;    /* 1 if the row-ordered pass was fused                                */
 } gsr_solve_info;
 
 typedef struct gsr_handle gsr_handle;

@@ -20,6 +20,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a different build of the same source (e.g. a deliberately broken copy used to check that
+# the pins catch mistakes) can be swapped in for a test run
+_LIB = os.environ.get("GSR_ORACLE_LIB", _LIB)
 
 
 def build(force: bool = True) -> str:

@@ -73,9 +73,7 @@ class LstsqSolve(torch.autograd.Function):
             grad_vals = torch.empty(24 * m, dtype=torch.float64, device=g.device)
             gsr.gsr_grad_vals(h, r, mu, x, lam, grad_vals)
         grad_b = mu if ctx.needs_input_grad[1] else None
-        torch.cuda.current_stream().synchronize()
-        h.close()
-        ctx.h = None
+        # the handle stays open (backward may run again); it is released with the graph
         return grad_vals, grad_b, None, None, None, None
 
 

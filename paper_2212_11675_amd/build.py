@@ -24,6 +24,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
+    "-Wshadow",
+    "-Werror=shadow",
 ]
 
 

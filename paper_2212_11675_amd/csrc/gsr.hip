@@ -135,6 +135,9 @@ struct gsr_handle {
     int chunk1 = 16, chunk2s = 16, chunk2t = 16;
     int lds1 = 0, lds2 = 0;           // instrumental columns staged / privatized in LDS
     size_t lds1_bytes = 0, lds2_bytes = 0;
+    // fused row pass (aprod 1 + star-ordered part of aprod 2), used when n_instr fits LDS
+    int fused = 0, G12 = 1, chunk12 = 16, lds12_x = 0;
+    size_t lds12_bytes = 0;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
     double *dx = nullptr, *r = nullptr;  // refinement
     hipStream_t cap = nullptr;     // capture stream
@@ -203,6 +206,14 @@ void launch_aprod1(const gsr_handle* h, const VT* vals, const double* xx, double
                        h->lds1);
 }
 
+// x[ins0 .. glb0] += the blocks' instrumental/global sums in part_ig
+void launch_reduce(const gsr_handle* h, int nblocks, double* x, int check_stop, hipStream_t s) {
+    const int ncols = h->g.I + 1;
+    const int slices = std::max(1, std::min(32, nblocks / 8));
+    hipLaunchKernelGGL(k_reduce_partials, dim3((ncols + 255) / 256, slices), dim3(256), 0, s,
+                       ncols, nblocks, h->part_ig, x + h->g.ins0, h->st, check_stop);
+}
+
 // x += A^T y: star-ordered pass (astrometric, instrumental, global), reduction of the
 // instrumental/global block sums, attitude pass over the t-ordered copy.
 template <typename VT, int MODE>
@@ -211,12 +222,7 @@ void launch_aprod2(const gsr_handle* h, const VT* vals, const VT* attT, const do
     const Geo& g = h->g;
     hipLaunchKernelGGL((k_aprod2_star<VT, MODE>), dim3(h->G2s), dim3(kBlock2s), h->lds2_bytes, s,
                        g, vals, h->star, h->instr, y, x, h->st, h->part_ig, h->chunk2s, h->lds2);
-    if (h->lds2) {
-        const int ncols = g.I + 1;
-        hipLaunchKernelGGL(k_reduce_partials, dim3((ncols + 255) / 256), dim3(256), 0, s, ncols,
-                           h->G2s, h->part_ig, x + g.ins0, h->st,
-                           (int)(MODE == A2_LSQR || MODE == A2_LSQR_T));
-    }
+    if (h->lds2) launch_reduce(h, h->G2s, x, (int)(MODE == A2_LSQR || MODE == A2_LSQR_T), s);
     hipLaunchKernelGGL((k_aprod2_att<VT, MODE>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
                        h->rowT, h->tT, y, x, h->st, h->chunk2t);
 }
@@ -287,19 +293,44 @@ void mark(hipEvent_t e, hipStream_t s) {
     if (e) (void)hipEventRecord(e, s);
 }
 
+// Fused row pass: u~ = sv A xt - alpha su u~ and s += A^T u~ (astrometric, instrumental,
+// global), then the instrumental/global reduction and the attitude pass (s += A_att^T u~).
+template <typename VT>
+void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u, double* s_acc,
+                  hipStream_t s, const IterEvents* ev) {
+    const Geo& g = h->g;
+    if (ev) mark(ev->a1_begin, s);
+    hipLaunchKernelGGL((k_aprod12<VT, 2>), dim3(h->G12), dim3(1024), h->lds12_bytes, s, g, vals,
+                       h->star, h->att, h->instr, h->xt, u, s_acc, h->st, h->partA, h->part_ig,
+                       h->chunk12, h->lds12_x);
+    if (ev) mark(ev->a1_end, s);
+    if (ev) mark(ev->a2_begin, s);
+    launch_reduce(h, h->G12, s_acc, 1, s);
+    hipLaunchKernelGGL((k_aprod2_att<VT, A2_LSQR>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
+                       h->rowT, h->tT, u, s_acc, h->st, h->chunk2t);
+    if (ev) mark(ev->a2_end, s);
+}
+
 template <typename VT>
 void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
                    const double* p, hipStream_t s, const IterEvents* ev = nullptr) {
     const Geo& g = h->g;
-    // beta u = A (p o v) - alpha u        (xt = p o v~ from the previous vector step)
-    if (ev) mark(ev->a1_begin, s);
-    launch_aprod1<VT, A1_LSQR>(h, vals, h->xt, w.u, nullptr, s);
-    if (ev) mark(ev->a1_end, s);
-    hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
-    // alpha v = p o A^T u - beta v, with the pending z/w update of the previous iteration
-    if (ev) mark(ev->a2_begin, s);
-    launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
-    if (ev) mark(ev->a2_end, s);
+    if (h->fused) {
+        // one read of every row: beta u = A (p o v) - alpha u and s = A^T u~ (unnormalized)
+        launch_fused<VT>(h, vals, attT, w.u, h->s, s, ev);
+        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G12);
+    } else {
+        // beta u = A (p o v) - alpha u        (xt = p o v~ from the previous vector step)
+        if (ev) mark(ev->a1_begin, s);
+        launch_aprod1<VT, A1_LSQR>(h, vals, h->xt, w.u, nullptr, s);
+        if (ev) mark(ev->a1_end, s);
+        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+        // s = A^T u~ (unnormalized)
+        if (ev) mark(ev->a2_begin, s);
+        launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
+        if (ev) mark(ev->a2_end, s);
+    }
+    // alpha v = p o (s / beta) - beta v, with the pending z/w update of the previous iteration
     hipLaunchKernelGGL(k_vec_v<false>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
                        w.z, h->xt, h->st, h->partB);
     hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn,
@@ -429,10 +460,10 @@ gsr_status read_info(gsr_handle* h, gsr_solve_info* info, hipStream_t s,
     const LsqrState& t = *h->st_host;
     if (info) {
         std::memset(info, 0, sizeof *info);
-        info->ms_aprod1 = prof.ms1;
-        info->ms_aprod2 = prof.ms2;
-        info->n_aprod1 = prof.n;
-        info->n_aprod2 = prof.n;
+        info->ms_pass1 = prof.ms1;
+        info->ms_pass2 = prof.ms2;
+        info->n_pass = prof.n;
+        info->fused = h->fused;
         info->itn = t.itn;
         info->istop = t.istop;
         info->n_refine = 1;
@@ -628,16 +659,25 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         h->G1 = grid(o1, kBlock1, h->chunk1);
         h->G2s = grid(o2s, kBlock2s, h->chunk2s);
         h->G2t = grid(o2t, kBlock2t, h->chunk2t);
+        h->fused = h->lds2;
+        if (h->fused) {
+            const size_t lds_max = 160 * 1024;
+            h->lds12_x = sizeof(double) * (2 * (size_t)g.I + 1) <= lds_max;
+            h->lds12_bytes = sizeof(double) * ((size_t)g.I + 1 + (h->lds12_x ? g.I : 0));
+            const int o12 = occ((const void*)k_aprod12<double, 2>, 1024, h->lds12_bytes);
+            h->chunk12 = chunk_for(o12 * n_cu * 1024 / kWave);
+            h->G12 = grid(o12, 1024, h->chunk12);
+        }
     }
     gsr_status st;
     if ((st = dalloc(&h->p64, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->s, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->xt, g.n)) != GSR_OK) return bail(st);
-    const int part_len = std::max(std::max(h->G1, h->Gm), h->Gn);
+    const int part_len = std::max(std::max(std::max(h->G1, h->Gm), h->Gn), h->G12);
     if ((st = dalloc(&h->partA, part_len)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->partB, 4 * (size_t)part_len)) != GSR_OK) return bail(st);
-    if (h->lds2 &&
-        (st = dalloc(&h->part_ig, (size_t)h->G2s * (g.I + 1))) != GSR_OK)
+    if (h->lds2 && (st = dalloc(&h->part_ig, (size_t)std::max(h->G2s, h->G12) * (g.I + 1))) !=
+                       GSR_OK)
         return bail(st);
     if ((st = dalloc(&h->st, 1)) != GSR_OK) return bail(st);
     {

@@ -152,6 +152,7 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
     const bool pending = !INIT && st->pending;
     const double f1 = st->f1, f2 = st->f2, sv = st->sv;
     const double c1 = INIT ? 0.0 : st->beta * st->sv;
+    const double su = st->su;  // s holds A^T u~ unnormalized
     double avv = 0.0, azz = 0.0, azw = 0.0, aww = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
@@ -159,7 +160,7 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
         s[j] = 0.0;
         double vn;
         if (INIT) {
-            vn = p[j] * sj;
+            vn = p[j] * (su * sj);
             z[j] = 0.0;
             w[j] = 0.0;
         } else {
@@ -174,7 +175,7 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
                 azw = fma(zj, wn, azw);
                 aww = fma(wn, wn, aww);
             }
-            vn = p[j] * sj - c1 * vj;
+            vn = p[j] * (su * sj) - c1 * vj;
         }
         v[j] = vn;
         xt[j] = p[j] * vn;

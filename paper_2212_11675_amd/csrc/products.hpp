@@ -30,10 +30,86 @@ __device__ __forceinline__ double ld_val(const float* __restrict__ p) {
     return (double)__builtin_nontemporal_load(p);
 }
 
+// Cross-lane moves of a double with a DPP control (both 32-bit halves).
+// quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E; row_ror:4 = 0x124, row_ror:8 = 0x128.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi2, lo2);
+}
+
+// Sum over the four lanes of a quad, result in all four.
 __device__ __forceinline__ double quad_sum(double v) {
-    v += __shfl_xor(v, 1, kWave);
-    v += __shfl_xor(v, 2, kWave);
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
     return v;
+}
+
+// Sum over the lanes with the same lane % STRIDE, result in all of them.
+template <int STRIDE>
+__device__ __forceinline__ double group_sum(double v) {
+    int off = STRIDE;
+    if (STRIDE == 4) {  // within each 16-lane row by rotation, then across rows
+        v += dpp_f64<0x128>(v);
+        v += dpp_f64<0x124>(v);
+        off = 16;
+    }
+    for (; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Runs of equal keys over the row groups of a wave (lane = STRIDE * group + q; keys sorted
+// within the step, -1 for rows that take no part).  acc[] holds each lane's share of the
+// open run `ckey`.  A step whose rows all continue the open run only adds; when runs end,
+// their sums are reduced over the row groups and passed to flush(key, sums) -- called by
+// every lane, with the totals valid in all of them -- and the step's last run stays open.
+template <int NV, int STRIDE, typename F>
+__device__ __forceinline__ void run_step(int32_t key, const double (&v)[NV], double (&acc)[NV],
+                                         int32_t& ckey, F&& flush) {
+    const uint64_t valid = __ballot(key >= 0);
+    if (valid == 0) return;
+    // lane indices below are wave-uniform: read the key with v_readlane (no LDS round trip)
+    const int32_t kfirst =
+        __builtin_amdgcn_readlane(key, __ffsll((unsigned long long)valid) - 1);
+    const int32_t klast = __builtin_amdgcn_readlane(key, 63 - __clzll((unsigned long long)valid));
+    if (kfirst == ckey && klast == ckey) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] += v[j];
+        return;
+    }
+    double red[NV];
+    if (ckey >= 0) {  // the open run ends in this step (or ended at its start)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) red[j] = group_sum<STRIDE>(acc[j] + (key == ckey ? v[j] : 0.0));
+        flush(ckey, red);
+    }
+    auto next_after = [&](int32_t k) {
+        const uint64_t gt = __ballot(key > k);
+        return (int32_t)__builtin_amdgcn_readlane(key, __ffsll((unsigned long long)gt) - 1);
+    };
+    int32_t k = (kfirst == ckey) ? next_after(ckey) : kfirst;
+    while (k != klast) {  // runs that start and end inside the step
+#pragma unroll
+        for (int j = 0; j < NV; ++j) red[j] = group_sum<STRIDE>(key == k ? v[j] : 0.0);
+        flush(k, red);
+        k = next_after(k);
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = (key == klast) ? v[j] : 0.0;
+    ckey = klast;
+}
+
+// Close the open run at the end of a chunk.
+template <int NV, int STRIDE, typename F>
+__device__ __forceinline__ void run_close(double (&acc)[NV], int32_t& ckey, F&& flush) {
+    if (ckey < 0) return;
+    double red[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) red[j] = group_sum<STRIDE>(acc[j]);
+    flush(ckey, red);
+    ckey = -1;
 }
 
 // Inclusive segmented scan over the row groups of a wave (lane = STRIDE * group + q),
@@ -147,8 +223,9 @@ static __global__ __launch_bounds__(512) void k_aprod1(
 
 // ---------------------------------------------------------------------------------------
 // aprod 2, star-ordered pass: astrometric, instrumental and global columns.
-//   x[col(i,k)] += A[i,k] yy_i,  yy_i = y[i] (A2_ADD), su y[i] (A2_LSQR), sv y[i]
-//   (A2_LSQR_T), or the contribution is A[i,k]^2 (A2_SQ, column norms).
+//   x[col(i,k)] += A[i,k] yy_i,  yy_i = y[i] (A2_ADD; A2_LSQR, where y = u~ unnormalized and
+//   the vector step applies 1/beta), sv y[i] (A2_LSQR_T), or the contribution is A[i,k]^2
+//   (A2_SQ, column norms).  LSQR modes return at once when the stop flag is set.
 // Astrometric: a star's rows are contiguous; a run is written once by the wave that ends it,
 // with a plain read-modify-write when the whole star lies inside the wave's chunk and an
 // atomic add when the star continues into a neighbouring chunk.
@@ -159,7 +236,7 @@ enum { A2_ADD = 0, A2_LSQR = 1, A2_LSQR_T = 2, A2_SQ = 3 };
 
 template <int MODE>
 __device__ __forceinline__ double a2_scale(const LsqrState* __restrict__ st) {
-    return MODE == A2_LSQR ? st->su : (MODE == A2_LSQR_T ? st->sv : 1.0);
+    return MODE == A2_LSQR_T ? st->sv : 1.0;  // A2_LSQR: unnormalized (1/beta in k_vec_v)
 }
 
 template <int MODE>
@@ -195,17 +272,23 @@ static __global__ __launch_bounds__(512) void k_aprod2_star(
             (r_beg > 0 && star[r_beg - 1] == star[r_beg]) ? star[r_beg] : -1;
         const int32_t shared_last =
             (r_end < g.m && star[r_end] == star[r_end - 1]) ? star[r_end - 1] : -1;
-        auto flush = [&](int32_t key, double v0, double v1) {
+        // finished star: row group 0 writes it (astro q; astro 4 from q = 0).  In the LSQR and
+        // column-norm modes the target starts at zero, so an owned star is simply stored.
+        auto flush = [&](int32_t key, const double (&t)[2]) {
+            if (rg != 0) return;
             double* xa = x + (int64_t)kAstro * key;
             if (key == shared_first || key == shared_last) {
-                atomic_add_f64(xa + q, v0);
-                if (q == 0) atomic_add_f64(xa + 4, v1);
+                atomic_add_f64(xa + q, t[0]);
+                if (q == 0) atomic_add_f64(xa + 4, t[1]);
+            } else if (MODE == A2_ADD) {
+                xa[q] += t[0];
+                if (q == 0) xa[4] += t[1];
             } else {
-                xa[q] += v0;
-                if (q == 0) xa[4] += v1;
+                xa[q] = t[0];
+                if (q == 0) xa[4] = t[1];
             }
         };
-        double c0 = 0.0, c1 = 0.0;  // carry of the open run (astro q; astro 4 on q = 0)
+        double acc[2] = {0.0, 0.0};  // this lane's share of the open run
         int32_t ckey = -1;
         for (int64_t r0 = r_beg; r0 < r_end; r0 += kStepRows) {
             const int64_t r = r0 + rg;
@@ -236,23 +319,9 @@ static __global__ __launch_bounds__(512) void k_aprod2_star(
                     gacc += p5;
                 }
             }
-            // close or continue the run carried from the previous step
-            if (rg == 0 && ckey >= 0) {
-                if (key == ckey) {
-                    v[0] += c0;
-                    v[1] += c1;
-                } else {
-                    flush(ckey, c0, c1);
-                }
-            }
-            seg_scan_rows<2>(key, v, lane);
-            const int32_t knext = __shfl_down(key, kQuad, kWave);
-            if (valid && rg < kStepRows - 1 && knext != key) flush(key, v[0], v[1]);
-            c0 = __shfl(v[0], kWave - kQuad + q, kWave);
-            c1 = __shfl(v[1], kWave - kQuad + q, kWave);
-            ckey = __shfl(key, kWave - kQuad, kWave);
+            run_step<2, kQuad>(key, v, acc, ckey, flush);
         }
-        if (rg == 0 && ckey >= 0) flush(ckey, c0, c1);
+        run_close<2, kQuad>(acc, ckey, flush);
     }
     const double gs = wave_sum(gacc);
     if (lane == 0) atomicAdd(lglob, gs);
@@ -266,15 +335,144 @@ static __global__ __launch_bounds__(512) void k_aprod2_star(
 }
 
 // x[ins0 + c] += sum_b part[b][c] for the n_instr + 1 instrumental and global columns.
+// blockIdx.y takes a slice of the blocks; slices meet in one atomic add per column.
 static __global__ void k_reduce_partials(int ncols, int nblocks, const double* __restrict__ part,
                                          double* __restrict__ x, const LsqrState* __restrict__ st,
                                          int check_stop) {
     if (check_stop && st->stop) return;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols) return;
+    const int per = (nblocks + gridDim.y - 1) / gridDim.y;
+    const int b0 = blockIdx.y * per, b1 = min(nblocks, b0 + per);
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * ncols + c];
-    x[c] += s;
+    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * ncols + c];
+    if (gridDim.y == 1) {
+        x[c] += s;
+    } else if (b0 < b1) {
+        atomic_add_f64(x + c, s);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused LSQR u-step and star-ordered part of the following v-step (one read of each row):
+//   u~[r] = sv (A xt)[r] - alpha su u~[r]            (xt = p o v~, the previous v-step)
+//   s[c] += A[r,c] u~[r]   for the astrometric, instrumental and global columns
+// s is accumulated unnormalized (1/beta is applied by the vector step once beta is known);
+// the attitude columns of s come from k_aprod2_att on the t-ordered copy.  Block partials:
+// sum u~^2 -> partials[block], instrumental/global sums -> part[block][n_instr + 1].
+// U row steps are loaded before any of them is reduced (memory-level parallelism).
+template <typename VT, int U>
+static __global__ __launch_bounds__(1024) void k_aprod12(
+    Geo g, const VT* __restrict__ vals, const int32_t* __restrict__ star,
+    const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
+    const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
+    const LsqrState* __restrict__ st, double* __restrict__ partials,
+    double* __restrict__ part, int chunk_rows, int lds_x) {
+    extern __shared__ double lds[];  // [n_instr + 1] sums, then [n_instr] staged xt (lds_x)
+    __shared__ double sh[1024 / kWave];
+    if (st->stop) return;
+    const double xs = st->sv, ys = st->alpha * st->su;
+    double* lsum = lds;  // instrumental and global sums of the block
+    double* lxi = lds + g.I + 1;
+    for (int k = threadIdx.x; k <= g.I; k += blockDim.x) lsum[k] = 0.0;
+    if (lds_x)
+        for (int k = threadIdx.x; k < g.I; k += blockDim.x) lxi[k] = xx[g.ins0 + k];
+    __syncthreads();
+    const double* __restrict__ xi = lds_x ? lxi : xx + g.ins0;
+    const int lane = threadIdx.x % kWave, rg = lane / kQuad, q = lane % kQuad;
+    const int wpb = blockDim.x / kWave;
+    const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;
+    const double xglob = xx[g.glb0];
+    const int ia_off = (q == 0) ? 3 : q - 1;
+    const int ib_off = (q == 1 || q == 2) ? q + 3 : ia_off;
+    const int jatt = (q + 3) & 3;
+    double usq = 0.0, gacc = 0.0;
+    for (int64_t ch = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks;
+         ch += (int64_t)gridDim.x * wpb) {
+        const int64_t r_beg = ch * (int64_t)chunk_rows;
+        const int64_t r_end = min(r_beg + chunk_rows, g.m);
+        const int32_t shared_first =
+            (r_beg > 0 && star[r_beg - 1] == star[r_beg]) ? star[r_beg] : -1;
+        const int32_t shared_last =
+            (r_end < g.m && star[r_end] == star[r_end - 1]) ? star[r_end - 1] : -1;
+        // finished star (s is zero before this pass: owned stars are stored)
+        auto flush = [&](int32_t key, const double (&t)[2]) {
+            if (rg != 0) return;
+            double* xa = s + (int64_t)kAstro * key;
+            if (key == shared_first || key == shared_last) {
+                atomic_add_f64(xa + q, t[0]);
+                if (q == 0) atomic_add_f64(xa + 4, t[1]);
+            } else {
+                xa[q] = t[0];
+                if (q == 0) xa[4] = t[1];
+            }
+        };
+        double acc[2] = {0.0, 0.0};
+        int32_t ckey = -1;
+        for (int64_t r0 = r_beg; r0 < r_end; r0 += kStepRows * U) {
+            double a[U][6], uo[U];
+            int32_t sr[U], tr[U], ia[U], ib[U];
+            bool valid[U];
+#pragma unroll
+            for (int w = 0; w < U; ++w) {
+                const int64_t r = r0 + w * kStepRows + rg;
+                valid[w] = r < r_end;
+                const int64_t rr = valid[w] ? r : r_beg;  // in-bounds stand-in row
+                const VT* __restrict__ row = vals + rr * kPar + q;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) a[w][k] = ld_val(row + 4 * k);
+                sr[w] = star[rr];
+                tr[w] = att[rr];
+                ia[w] = instr[rr * kInstr + ia_off];
+                ib[w] = instr[rr * kInstr + ib_off];
+                uo[w] = uu[rr];
+            }
+#pragma unroll
+            for (int w = 0; w < U; ++w) {
+                const int64_t r = r0 + w * kStepRows + rg;
+                // aprod 1 part: the row's dot product, spread over the quad
+                const int64_t ca = (int64_t)kAstro * sr[w];
+                double sum = a[w][0] * xx[ca + q];
+                if (q == 0) sum = fma(a[w][1], xx[ca + 4], sum);
+                const double* __restrict__ xa = xx + g.att0 + tr[w] + jatt;
+#pragma unroll
+                for (int ax = 0; ax < kAxes; ++ax) {
+                    const double c = (q == 0) ? a[w][ax + 2] : a[w][ax + 1];
+                    sum = fma(c, xa[(int64_t)ax * g.T], sum);
+                }
+                const double regA = (q == 0) ? a[w][5] : a[w][4];
+                sum = fma(regA, xi[ia[w]], sum);
+                if (q == 1 || q == 2) sum = fma(a[w][5], xi[ib[w]], sum);
+                if (q == 3) sum = fma(a[w][5], xglob, sum);
+                sum = quad_sum(sum);
+                const double un = (ys != 0.0) ? xs * sum - ys * uo[w] : xs * sum;
+                int32_t key = -1;
+                double v[2] = {0.0, 0.0};
+                if (valid[w]) {
+                    if (q == 0) {
+                        uu[r] = un;
+                        usq = fma(un, un, usq);
+                    }
+                    key = sr[w];
+                    v[0] = a[w][0] * un;
+                    v[1] = (q == 0) ? a[w][1] * un : 0.0;
+                    atomicAdd(lsum + ia[w], regA * un);
+                    if (q == 1 || q == 2) atomicAdd(lsum + ib[w], a[w][5] * un);
+                    if (q == 3) gacc = fma(a[w][5], un, gacc);
+                }
+                // aprod 2 part, astrometric columns: runs of equal star
+                run_step<2, kQuad>(key, v, acc, ckey, flush);
+            }
+        }
+        run_close<2, kQuad>(acc, ckey, flush);
+    }
+    const double gs = wave_sum(gacc);
+    if (lane == 0) atomicAdd(lsum + g.I, gs);
+    const double tot = block_sum<1024>(usq, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    __syncthreads();
+    double* dst = part + (int64_t)blockIdx.x * (g.I + 1);
+    for (int k = threadIdx.x; k <= g.I; k += blockDim.x) dst[k] = lsum[k];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -293,44 +491,46 @@ static __global__ __launch_bounds__(256) void k_aprod2_att(
     const int wpb = blockDim.x / kWave;
     const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;
     double* __restrict__ xatt = x + g.att0 + q;
-    auto flush = [&](int32_t key, const double (&v)[3]) {
+    auto flush = [&](int32_t key, const double (&t)[3]) {
+        if (rg != 0) return;
 #pragma unroll
-        for (int ax = 0; ax < kAxes; ++ax) atomic_add_f64(xatt + (int64_t)ax * g.T + key, v[ax]);
+        for (int ax = 0; ax < kAxes; ++ax) atomic_add_f64(xatt + (int64_t)ax * g.T + key, t[ax]);
     };
     for (int64_t ch = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks;
          ch += (int64_t)gridDim.x * wpb) {
         const int64_t k_end = min((ch + 1) * (int64_t)chunk_rows, g.m);
-        double c[3] = {0.0, 0.0, 0.0};
+        const int64_t k_beg = ch * (int64_t)chunk_rows;
+        double acc[3] = {0.0, 0.0, 0.0};
         int32_t ckey = -1;
-        for (int64_t k0 = ch * (int64_t)chunk_rows; k0 < k_end; k0 += kStepRows) {
-            const int64_t k = k0 + rg;
-            const bool valid = k < k_end;
-            int32_t key = -1;
-            double v[3] = {0.0, 0.0, 0.0};
-            if (valid) {
-                key = tT[k];
-                const double yy = (MODE == A2_SQ) ? 0.0 : ysc * y[rowT[k]];
-                const VT* __restrict__ a = attT + k * (kAxes * kParAxis) + q;
+        constexpr int U = 2;  // row steps loaded before any is reduced
+        for (int64_t k0 = k_beg; k0 < k_end; k0 += kStepRows * U) {
+            int32_t kt[U];
+            double va[U][kAxes], yy[U];
+            bool valid[U];
 #pragma unroll
-                for (int ax = 0; ax < kAxes; ++ax)
-                    v[ax] = contrib<MODE>(ld_val(a + kParAxis * ax), yy);
+            for (int w = 0; w < U; ++w) {
+                const int64_t k = k0 + w * kStepRows + rg;
+                valid[w] = k < k_end;
+                const int64_t kk = valid[w] ? k : k_beg;  // in-bounds stand-in
+                kt[w] = tT[kk];
+                yy[w] = (MODE == A2_SQ) ? 0.0 : ysc * y[rowT[kk]];
+                const VT* __restrict__ a = attT + kk * (kAxes * kParAxis) + q;
+#pragma unroll
+                for (int ax = 0; ax < kAxes; ++ax) va[w][ax] = ld_val(a + kParAxis * ax);
             }
-            if (rg == 0 && ckey >= 0) {
-                if (key == ckey) {
 #pragma unroll
-                    for (int ax = 0; ax < kAxes; ++ax) v[ax] += c[ax];
-                } else {
-                    flush(ckey, c);
+            for (int w = 0; w < U; ++w) {
+                int32_t key = -1;
+                double v[3] = {0.0, 0.0, 0.0};
+                if (valid[w]) {
+                    key = kt[w];
+#pragma unroll
+                    for (int ax = 0; ax < kAxes; ++ax) v[ax] = contrib<MODE>(va[w][ax], yy[w]);
                 }
+                run_step<3, kQuad>(key, v, acc, ckey, flush);
             }
-            seg_scan_rows<3>(key, v, lane);
-            const int32_t knext = __shfl_down(key, kQuad, kWave);
-            if (valid && rg < kStepRows - 1 && knext != key) flush(key, v);
-#pragma unroll
-            for (int ax = 0; ax < kAxes; ++ax) c[ax] = __shfl(v[ax], kWave - kQuad + q, kWave);
-            ckey = __shfl(key, kWave - kQuad, kWave);
         }
-        if (rg == 0 && ckey >= 0) flush(ckey, c);
+        run_close<3, kQuad>(acc, ckey, flush);
     }
 }
 

@@ -62,9 +62,9 @@ class SolveInfo(ctypes.Structure):
                 ("n_refine", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("rnorm", ctypes.c_double), ("arnorm", ctypes.c_double),
                 ("anorm", ctypes.c_double), ("znorm", ctypes.c_double),
-                ("bnorm", ctypes.c_double), ("ms_aprod1", ctypes.c_double),
-                ("ms_aprod2", ctypes.c_double), ("n_aprod1", ctypes.c_int32),
-                ("n_aprod2", ctypes.c_int32)]
+                ("bnorm", ctypes.c_double), ("ms_pass1", ctypes.c_double),
+                ("ms_pass2", ctypes.c_double), ("n_pass", ctypes.c_int32),
+                ("fused", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

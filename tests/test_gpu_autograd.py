@@ -99,5 +99,6 @@ def test_gradcheck_tiny():
                          .standard_normal(S.m)).to(dev)
     vals = t["vals"].clone().requires_grad_(True)
     b = b.clone().requires_grad_(True)
+    # device atomics reorder the column sums: repeated backward passes agree to rounding only
     assert torch.autograd.gradcheck(lambda v, bb: gad.lstsq(v, bb, st), (vals, b), eps=1e-6,
-                                    atol=1e-6, rtol=1e-5)
+                                    atol=1e-6, rtol=1e-5, nondet_tol=1e-12)
