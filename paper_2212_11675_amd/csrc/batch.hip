@@ -37,6 +37,7 @@ struct SysDesc {
     int32_t T, I;
     int32_t chunk0, nchunk;    // row chunks of the system
     int32_t tile0, ntile;      // column tiles of the system
+    int32_t bchunk0, nbchunk;  // block chunks of the system
 };
 
 struct Seg {
@@ -169,7 +170,7 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
         if (MODE == A2_LSQR) {
             const LsqrState* p = st + (int64_t)cur * K + j;
             live = !p->stop;
-            ysc = p->su;
+            ysc = 1.0;  // u~ unnormalized; k_bvec_v applies 1/beta
         }
         // this wave's contiguous sub-range of the block chunk
         const int64_t len = c.e1 - c.e0;
@@ -182,17 +183,23 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
             (r_beg < r_end && r_end < sys_end && star[r_end] == star[r_end - 1]) ? star[r_end - 1]
                                                                                 : -1;
         double* __restrict__ Xa = X + d.col0 * K + j;
-        auto flush = [&](int32_t key, const double (&v)[kAstro]) {
+        // finished star: the lanes of row group 0 write it (S starts at zero in the LSQR and
+        // column-norm modes, so an owned star is stored)
+        auto flush = [&](int32_t key, const double (&t)[kAstro]) {
+            if (rr != 0 || !live) return;
             double* xa = Xa + (int64_t)kAstro * key * K;
             if (key == shared_first || key == shared_last) {
 #pragma unroll
-                for (int q = 0; q < kAstro; ++q) atomic_add_f64(xa + q * K, v[q]);
+                for (int q = 0; q < kAstro; ++q) atomic_add_f64(xa + q * K, t[q]);
+            } else if (MODE == A2_ADD) {
+#pragma unroll
+                for (int q = 0; q < kAstro; ++q) xa[q * K] += t[q];
             } else {
 #pragma unroll
-                for (int q = 0; q < kAstro; ++q) xa[q * K] += v[q];
+                for (int q = 0; q < kAstro; ++q) xa[q * K] = t[q];
             }
         };
-        double cv[kAstro] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double acc[kAstro] = {0.0, 0.0, 0.0, 0.0, 0.0};
         int32_t ckey = -1;
         for (int64_t r0 = r_beg; r0 < r_end; r0 += RS) {
             const int64_t r = r0 + rr;
@@ -212,22 +219,140 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
                 }
                 gacc += contrib<MODE>(ld_val(row + 23), yy);
             }
-            if (rr == 0 && ckey >= 0) {
-                if (key == ckey) {
-#pragma unroll
-                    for (int q = 0; q < kAstro; ++q) v[q] += cv[q];
-                } else {
-                    flush(ckey, cv);
-                }
-            }
-            seg_scan_rows<kAstro, K>(key, v, lane);
-            const int32_t knext = __shfl_down(key, K, kWave);
-            if (valid && rr < RS - 1 && knext != key) flush(key, v);
-#pragma unroll
-            for (int q = 0; q < kAstro; ++q) cv[q] = __shfl(v[q], kWave - K + j, kWave);
-            ckey = __shfl(key, kWave - K, kWave);
+            run_step<kAstro, K>(key, v, acc, ckey, flush);
         }
-        if (rr == 0 && ckey >= 0) flush(ckey, cv);
+        run_close<kAstro, K>(acc, ckey, flush);
+    }
+    if (cur >= 0) flush_lds();
+}
+
+// Fused batched row pass: for every (row, rhs j) of a block chunk
+//   U[r, j] = sv_j (A XT)[r, j] - alpha_j su_j U[r, j]
+// and S += A^T U (astrometric: run accumulators; instrumental/global: LDS of the current
+// system), reading each row once.  Sum U^2 per (block chunk, j) -> partials.
+template <typename VT, int K>
+static __global__ __launch_bounds__(512) void k_baprod12(
+    const SysDesc* __restrict__ sys, const Seg* __restrict__ bchunks, int nbchunks,
+    const VT* __restrict__ vals, const int32_t* __restrict__ star,
+    const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
+    const double* __restrict__ XT, double* __restrict__ U, double* __restrict__ S,
+    const LsqrState* __restrict__ st, double* __restrict__ partials, int max_instr) {
+    extern __shared__ double lds[];  // [(max_instr + 1) * K] sums, then [K] block sum U^2
+    constexpr int RS = kWave / K;
+    const int lane = threadIdx.x % kWave, rr = lane / K, j = lane % K;
+    const int w = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+    const int per = (nbchunks + gridDim.x - 1) / gridDim.x;
+    const int bc_beg = blockIdx.x * per, bc_end = min(nbchunks, bc_beg + per);
+    const int nl = (max_instr + 1) * K;
+    double* lusq = lds + nl;
+    for (int e = threadIdx.x; e < nl + K; e += blockDim.x) lds[e] = 0.0;
+    __syncthreads();
+    int cur = -1;
+    SysDesc d = {};
+    double gacc = 0.0;
+    auto flush_lds = [&]() {
+        double gs = gacc;
+#pragma unroll
+        for (int off = K; off < kWave; off <<= 1) gs += __shfl_xor(gs, off, kWave);
+        if (lane < K) atomicAdd(lds + d.I * K + j, gs);
+        gacc = 0.0;
+        __syncthreads();
+        const int ne = (d.I + 1) * K;
+        double* xi = S + (d.col0 + d.ins0) * K;  // instrumental then global: contiguous
+        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+            const double v = lds[e];
+            if (v != 0.0) atomic_add_f64(xi + e, v);
+            lds[e] = 0.0;
+        }
+        __syncthreads();
+    };
+    for (int bc = bc_beg; bc < bc_end; ++bc) {
+        const Seg c = bchunks[bc];
+        if (c.sys != cur) {
+            if (cur >= 0) flush_lds();
+            cur = c.sys;
+            d = sys[cur];
+        }
+        const LsqrState* ps = st + (int64_t)cur * K + j;
+        const bool live = !ps->stop;
+        const double xs = ps->sv, ys = ps->alpha * ps->su;
+        const int64_t len = c.e1 - c.e0;
+        const int64_t sub = ((len + wpb - 1) / wpb + RS - 1) / RS * RS;
+        const int64_t r_beg = min(c.e1, c.e0 + w * sub), r_end = min(c.e1, r_beg + sub);
+        const int64_t sys_end = d.row0 + d.m;
+        const int32_t shared_first =
+            (r_beg < r_end && r_beg > d.row0 && star[r_beg - 1] == star[r_beg]) ? star[r_beg] : -1;
+        const int32_t shared_last =
+            (r_beg < r_end && r_end < sys_end && star[r_end] == star[r_end - 1]) ? star[r_end - 1]
+                                                                                : -1;
+        const double* __restrict__ Xs = XT + d.col0 * K + j;
+        double* __restrict__ Sa = S + d.col0 * K + j;
+        auto flush = [&](int32_t key, const double (&t)[kAstro]) {
+            if (rr != 0 || !live) return;
+            double* xa = Sa + (int64_t)kAstro * key * K;
+            if (key == shared_first || key == shared_last) {
+#pragma unroll
+                for (int q = 0; q < kAstro; ++q) atomic_add_f64(xa + q * K, t[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < kAstro; ++q) xa[q * K] = t[q];  // S is zero here
+            }
+        };
+        double acc[kAstro] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        int32_t ckey = -1;
+        double usq = 0.0;
+        for (int64_t r0 = r_beg; r0 < r_end; r0 += RS) {
+            const int64_t r = r0 + rr;
+            const bool valid = live && r < r_end;
+            int32_t key = -1;
+            double v[kAstro] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (valid) {
+                const VT* __restrict__ row = vals + r * kPar;
+                double a[kPar];
+#pragma unroll
+                for (int k = 0; k < kPar; ++k) a[k] = ld_val(row + k);
+                const int32_t sr = star[r], tr = att[r];
+                int32_t ins[kInstr];
+#pragma unroll
+                for (int k = 0; k < kInstr; ++k) ins[k] = instr[r * kInstr + k];
+                double sum = 0.0;
+#pragma unroll
+                for (int k = 0; k < kAstro; ++k)
+                    sum = fma(a[k], Xs[((int64_t)kAstro * sr + k) * K], sum);
+#pragma unroll
+                for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                    for (int k = 0; k < kParAxis; ++k)
+                        sum = fma(a[kAstro + ax * kParAxis + k],
+                                  Xs[(d.att0 + (int64_t)ax * d.T + tr + k) * K], sum);
+#pragma unroll
+                for (int k = 0; k < kInstr; ++k)
+                    sum = fma(a[17 + k], Xs[(d.ins0 + ins[k]) * K], sum);
+                sum = fma(a[23], Xs[d.glb0 * K], sum);
+                double* up = U + r * K + j;
+                const double un = (ys != 0.0) ? xs * sum - ys * *up : xs * sum;
+                *up = un;
+                usq = fma(un, un, usq);
+                key = sr;
+#pragma unroll
+                for (int q = 0; q < kAstro; ++q) v[q] = a[q] * un;
+#pragma unroll
+                for (int q = 0; q < kInstr; ++q) atomicAdd(lds + ins[q] * K + j, a[17 + q] * un);
+                gacc = fma(a[23], un, gacc);
+            }
+            run_step<kAstro, K>(key, v, acc, ckey, flush);
+        }
+        run_close<kAstro, K>(acc, ckey, flush);
+        // block sum of U^2 for this block chunk
+#pragma unroll
+        for (int off = K; off < kWave; off <<= 1) usq += __shfl_xor(usq, off, kWave);
+        if (lane < K) atomicAdd(lusq + j, usq);
+        __syncthreads();
+        if (threadIdx.x < K) {
+            partials[(int64_t)bc * K + threadIdx.x] = lusq[threadIdx.x];
+            lusq[threadIdx.x] = 0.0;
+        }
+        __syncthreads();
     }
     if (cur >= 0) flush_lds();
 }
@@ -251,19 +376,20 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
         if (MODE == A2_LSQR) {
             const LsqrState* p = st + (int64_t)c.sys * K + j;
             live = !p->stop;
-            ysc = p->su;
+            ysc = 1.0;  // u~ unnormalized; k_bvec_v applies 1/beta
         }
         double* __restrict__ Xt = X + (d.col0 + d.att0) * K + j;
-        auto flush = [&](int32_t key, const double (&v)[NA]) {
+        auto flush = [&](int32_t key, const double (&t)[NA]) {
+            if (rr != 0 || !live) return;
 #pragma unroll
             for (int ax = 0; ax < kAxes; ++ax)
 #pragma unroll
                 for (int q = 0; q < kParAxis; ++q)
-                    atomic_add_f64(Xt + ((int64_t)ax * d.T + key + q) * K, v[ax * kParAxis + q]);
+                    atomic_add_f64(Xt + ((int64_t)ax * d.T + key + q) * K, t[ax * kParAxis + q]);
         };
-        double cv[NA];
+        double acc[NA];
 #pragma unroll
-        for (int q = 0; q < NA; ++q) cv[q] = 0.0;
+        for (int q = 0; q < NA; ++q) acc[q] = 0.0;
         int32_t ckey = -1;
         for (int64_t k0 = c.e0; k0 < c.e1; k0 += RS) {
             const int64_t k = k0 + rr;
@@ -279,22 +405,9 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
 #pragma unroll
                 for (int q = 0; q < NA; ++q) v[q] = contrib<MODE>(ld_val(a + q), yy);
             }
-            if (rr == 0 && ckey >= 0) {
-                if (key == ckey) {
-#pragma unroll
-                    for (int q = 0; q < NA; ++q) v[q] += cv[q];
-                } else {
-                    flush(ckey, cv);
-                }
-            }
-            seg_scan_rows<NA, K>(key, v, lane);
-            const int32_t knext = __shfl_down(key, K, kWave);
-            if (valid && rr < RS - 1 && knext != key) flush(key, v);
-#pragma unroll
-            for (int q = 0; q < NA; ++q) cv[q] = __shfl(v[q], kWave - K + j, kWave);
-            ckey = __shfl(key, kWave - K, kWave);
+            run_step<NA, K>(key, v, acc, ckey, flush);
         }
-        if (rr == 0 && ckey >= 0) flush(ckey, cv);
+        run_close<NA, K>(acc, ckey, flush);
     }
 }
 
@@ -364,6 +477,7 @@ static __global__ __launch_bounds__(256) void k_bvec_v(const Seg* __restrict__ t
         const bool pending = !INIT && ps->pending;
         const double f1 = ps->f1, f2 = ps->f2, sv = ps->sv;
         const double c1 = INIT ? 0.0 : ps->beta * ps->sv;
+        const double su = ps->su;  // S holds A^T u~ unnormalized
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t e = c.e0 * K + threadIdx.x; e < c.e1 * K; e += blockDim.x) {
             const double sj = S[e];
@@ -372,7 +486,7 @@ static __global__ __launch_bounds__(256) void k_bvec_v(const Seg* __restrict__ t
             const double pj = p[e / K];
             double vn;
             if (INIT) {
-                vn = pj * sj;
+                vn = pj * (su * sj);
                 Z[e] = 0.0;
                 Wv[e] = 0.0;
             } else {
@@ -387,7 +501,7 @@ static __global__ __launch_bounds__(256) void k_bvec_v(const Seg* __restrict__ t
                     acc[2] = fma(zj, wn, acc[2]);
                     acc[3] = fma(wn, wn, acc[3]);
                 }
-                vn = pj * sj - c1 * vj;
+                vn = pj * (su * sj) - c1 * vj;
             }
             V[e] = vn;
             XT[e] = pj * vn;
@@ -466,9 +580,10 @@ static __global__ __launch_bounds__(256) void k_bscal(LsqrState* __restrict__ st
     if (pair >= n_sys * K) return;
     const int sidx = pair / K, j = pair % K;
     const SysDesc d = sys[sidx];
-    const bool by_rows = (STEP == BS_INIT1 || STEP == BS_BETA);
-    const int first = by_rows ? d.chunk0 : d.tile0;
-    const int count = by_rows ? d.nchunk : d.ntile;
+    const bool by_rows = (STEP == BS_INIT1);
+    const bool by_bchunks = (STEP == BS_BETA);
+    const int first = by_bchunks ? d.bchunk0 : (by_rows ? d.chunk0 : d.tile0);
+    const int count = by_bchunks ? d.nbchunk : (by_rows ? d.nchunk : d.ntile);
     LsqrState* ps = st + pair;
     if (STEP == BS_INIT1) {
         const double ss = pair_sum<K>(part, 0, nseg, first, count, j);
@@ -556,6 +671,7 @@ using namespace gsr;
         gsr_status s_ = (call);      \
         if (s_ != GSR_OK) return s_; \
     } while (0)
+#define HIP_TRY_VOID(call) (void)(call)
 
 namespace {
 
@@ -630,8 +746,10 @@ gsr_status build_lists(gsr_batch* b, const Tuning& t, hipStream_t s) {
             ch.push_back({d.row0 + r, d.row0 + std::min<int64_t>(d.m, r + t.chunk_rows), i, 0});
         d.nchunk = (int)ch.size() - d.chunk0;
         const int64_t bl = (int64_t)t.chunk_rows * wpb;
+        d.bchunk0 = (int)bch.size();
         for (int64_t r = 0; r < d.m; r += bl)
             bch.push_back({d.row0 + r, d.row0 + std::min<int64_t>(d.m, r + bl), i, 0});
+        d.nbchunk = (int)bch.size() - d.bchunk0;
         d.tile0 = (int)tl.size();
         for (int64_t c = 0; c < d.n; c += kBTile)
             tl.push_back({d.col0 + c, d.col0 + std::min<int64_t>(d.n, c + kBTile), i, 0});
@@ -720,9 +838,15 @@ void bscal(gsr_batch* b, int step, int nseg, const gsr_solve_opts& o, hipStream_
 template <int K>
 void b_iteration(gsr_batch* b, hipStream_t s) {
     const dim3 tgrid((unsigned)std::min(b->ntiles, b->n_cu * 8));
-    blaunch_aprod1<A1_LSQR, K>(b, b->XT, b->U, nullptr, s);
-    bscal<K>(b, BS_BETA, b->nchunks, gsr_solve_opts{}, s);
-    blaunch_aprod2<A2_LSQR, K>(b, b->U, b->S, s);
+    // one read of every row: U = sv A XT - alpha su U and S = A^T U (star-ordered part)
+    const size_t lds = sizeof(double) * ((size_t)(b->max_instr + 1) * K + K);
+    hipLaunchKernelGGL((k_baprod12<double, K>), dim3(b->G2s), dim3(b->tune.star_block), lds, s,
+                       b->d_sys, b->bchunks, b->nbchunks, b->vals, b->star, b->att, b->instr,
+                       b->XT, b->U, b->S, b->st, b->part, b->max_instr);
+    hipLaunchKernelGGL((k_baprod2_att<double, A2_LSQR, K>), dim3(b->G2t), dim3(256), 0, s,
+                       b->d_sys, b->chunks, b->nchunks, b->attT, b->rowT, b->tT, b->U, b->S,
+                       b->st);
+    bscal<K>(b, BS_BETA, b->nbchunks, gsr_solve_opts{}, s);
     hipLaunchKernelGGL((k_bvec_v<false, K>), tgrid, dim3(256), 0, s, b->tiles, b->ntiles, b->S,
                        b->p, b->V, b->W, b->Z, b->XT, b->st, b->part);
     bscal<K>(b, BS_ALPHA, b->ntiles, gsr_solve_opts{}, s);
@@ -767,10 +891,20 @@ gsr_status autotune(gsr_batch* b, hipStream_t s) {
         float ms = 0.f;
         with_k(b->k, [&](auto kc) {
             constexpr int K = decltype(kc)::value;
+            // the two product passes of one iteration, on scratch contents (every pair's
+            // state is still zero here, so the values are zeros)
+            HIP_TRY_VOID(hipMemsetAsync(b->XT, 0, sizeof(double) * b->N * K, s));
+            HIP_TRY_VOID(hipMemsetAsync(b->U, 0, sizeof(double) * b->M * K, s));
+            const size_t lds = sizeof(double) * ((size_t)(b->max_instr + 1) * K + K);
             for (int rep = 0; rep < 3; ++rep) {
                 if (rep == 1) (void)hipEventRecord(e0, s);
-                blaunch_aprod1<A1_ADD, K>(b, b->V, b->U, nullptr, s);
-                blaunch_aprod2<A2_ADD, K>(b, b->U, b->S, s);
+                hipLaunchKernelGGL((k_baprod12<double, K>), dim3(b->G2s), dim3(t.star_block), lds,
+                                   s, b->d_sys, b->bchunks, b->nbchunks, b->vals, b->star,
+                                   b->att, b->instr, b->XT, b->U, b->S, b->st, b->part,
+                                   b->max_instr);
+                hipLaunchKernelGGL((k_baprod2_att<double, A2_LSQR, K>), dim3(b->G2t), dim3(256),
+                                   0, s, b->d_sys, b->chunks, b->nchunks, b->attT, b->rowT,
+                                   b->tT, b->U, b->S, b->st);
             }
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);

@@ -194,8 +194,8 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
     }
 }
 
-// Transposed operator, u-step after aprod 2 accumulated s = A^T (sv v~):
-//   u~ = p o s - alpha su u~ ; s = 0 ; xt = p o u~ ; partial sum u~^2.
+// Transposed operator, u-step after aprod 2 accumulated s = A^T v~ (unnormalized):
+//   u~ = p o (sv s) - alpha su u~ ; s = 0 ; xt = p o u~ ; partial sum u~^2.
 static __global__ __launch_bounds__(kBlock) void k_vec_tu(int64_t n, double* __restrict__ s,
                                                    const double* __restrict__ p,
                                                    double* __restrict__ u, double* __restrict__ xt,
@@ -204,12 +204,13 @@ static __global__ __launch_bounds__(kBlock) void k_vec_tu(int64_t n, double* __r
     __shared__ double sh[kBlock / kWave];
     if (st->stop) return;
     const double c1 = st->alpha * st->su;
+    const double sv = st->sv;  // s holds A^T v~ unnormalized
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
         const double sj = s[j];
         s[j] = 0.0;
-        const double un = p[j] * sj - c1 * u[j];
+        const double un = p[j] * (sv * sj) - c1 * u[j];
         u[j] = un;
         xt[j] = p[j] * un;
         acc = fma(un, un, acc);

@@ -223,9 +223,9 @@ static __global__ __launch_bounds__(512) void k_aprod1(
 
 // ---------------------------------------------------------------------------------------
 // aprod 2, star-ordered pass: astrometric, instrumental and global columns.
-//   x[col(i,k)] += A[i,k] yy_i,  yy_i = y[i] (A2_ADD; A2_LSQR, where y = u~ unnormalized and
-//   the vector step applies 1/beta), sv y[i] (A2_LSQR_T), or the contribution is A[i,k]^2
-//   (A2_SQ, column norms).  LSQR modes return at once when the stop flag is set.
+//   x[col(i,k)] += A[i,k] y[i]  (A2_ADD; A2_LSQR / A2_LSQR_T, where y is the unnormalized
+//   u~ or v~ and the following vector step applies 1/beta or 1/alpha), or the contribution is
+//   A[i,k]^2 (A2_SQ, column norms).  LSQR modes return at once when the stop flag is set.
 // Astrometric: a star's rows are contiguous; a run is written once by the wave that ends it,
 // with a plain read-modify-write when the whole star lies inside the wave's chunk and an
 // atomic add when the star continues into a neighbouring chunk.
@@ -236,7 +236,7 @@ enum { A2_ADD = 0, A2_LSQR = 1, A2_LSQR_T = 2, A2_SQ = 3 };
 
 template <int MODE>
 __device__ __forceinline__ double a2_scale(const LsqrState* __restrict__ st) {
-    return MODE == A2_LSQR_T ? st->sv : 1.0;  // A2_LSQR: unnormalized (1/beta in k_vec_v)
+    return 1.0;  // LSQR modes accumulate unnormalized (the vector step applies 1/beta, 1/alpha)
 }
 
 template <int MODE>
@@ -361,17 +361,27 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 // the attitude columns of s come from k_aprod2_att on the t-ordered copy.  Block partials:
 // sum u~^2 -> partials[block], instrumental/global sums -> part[block][n_instr + 1].
 // U row steps are loaded before any of them is reduced (memory-level parallelism).
-template <typename VT, int U>
+//
+// TRANS: the same pass for the transposed operator D A^T (the adjoint solve), where the
+// row-space vector is v~:  v~[r] = su (A xt)[r] - beta sv v~[r]  (xt = p o u~), preceded on
+// the same rows by the pending update z += f1 w; w = sv v~ - f2 w of the row-space z, w.
+// Partials then are 4 rows of gridDim: sum v~^2, sum z^2, sum z w, sum w^2.
+template <typename VT, int U, bool TRANS = false>
 static __global__ __launch_bounds__(1024) void k_aprod12(
     Geo g, const VT* __restrict__ vals, const int32_t* __restrict__ star,
     const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
     const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
     const LsqrState* __restrict__ st, double* __restrict__ partials,
-    double* __restrict__ part, int chunk_rows, int lds_x) {
+    double* __restrict__ part, int chunk_rows, int lds_x, double* __restrict__ ww_vec = nullptr,
+    double* __restrict__ zz_vec = nullptr) {
     extern __shared__ double lds[];  // [n_instr + 1] sums, then [n_instr] staged xt (lds_x)
     __shared__ double sh[1024 / kWave];
     if (st->stop) return;
-    const double xs = st->sv, ys = st->alpha * st->su;
+    const double xs = TRANS ? st->su : st->sv;
+    const double ys = TRANS ? st->beta * st->sv : st->alpha * st->su;
+    const bool pending = TRANS && st->pending;
+    const double f1 = st->f1, f2 = st->f2, svo = st->sv;
+    double zsq = 0.0, zw = 0.0, wsq = 0.0;
     double* lsum = lds;  // instrumental and global sums of the block
     double* lxi = lds + g.I + 1;
     for (int k = threadIdx.x; k <= g.I; k += blockDim.x) lsum[k] = 0.0;
@@ -450,6 +460,16 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
                 double v[2] = {0.0, 0.0};
                 if (valid[w]) {
                     if (q == 0) {
+                        if (TRANS && pending) {  // z, w updated with the old v~ of this row
+                            const double wo = ww_vec[r];
+                            const double zn = fma(f1, wo, zz_vec[r]);
+                            const double wn = svo * uo[w] - f2 * wo;
+                            zz_vec[r] = zn;
+                            ww_vec[r] = wn;
+                            zsq = fma(zn, zn, zsq);
+                            zw = fma(zn, wn, zw);
+                            wsq = fma(wn, wn, wsq);
+                        }
                         uu[r] = un;
                         usq = fma(un, un, usq);
                     }
@@ -470,6 +490,15 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     if (lane == 0) atomicAdd(lsum + g.I, gs);
     const double tot = block_sum<1024>(usq, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (TRANS) {
+        const int G = gridDim.x;
+        double t2 = block_sum<1024>(zsq, sh);
+        if (threadIdx.x == 0) partials[G + blockIdx.x] = t2;
+        t2 = block_sum<1024>(zw, sh);
+        if (threadIdx.x == 0) partials[2 * G + blockIdx.x] = t2;
+        t2 = block_sum<1024>(wsq, sh);
+        if (threadIdx.x == 0) partials[3 * G + blockIdx.x] = t2;
+    }
     __syncthreads();
     double* dst = part + (int64_t)blockIdx.x * (g.I + 1);
     for (int k = threadIdx.x; k <= g.I; k += blockDim.x) dst[k] = lsum[k];
