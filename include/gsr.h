@@ -207,7 +207,7 @@ typedef struct gsr_batch gsr_batch;
  *   row_offset  host [n_sys+1]: system s owns rows row_offset[s] .. row_offset[s+1]-1 of
  *               the concatenated arrays (row_offset[0] = 0).
  *   vals/star/att/instr  device, concatenated; indices are relative to each system.
- *   k           right-hand sides per system, 1..8.
+ *   k           right-hand sides per system, 1, 2, 4 or 8 (GSR_E_UNSUPPORTED otherwise).
  * Unknowns of system s occupy columns col_offset[s] .. col_offset[s+1]-1 of the batched
  * unknown vector (gsr_batch_col_offsets), each system in the column order above.
  * Synchronizes `stream`.

@@ -295,20 +295,24 @@ void mark(hipEvent_t e, hipStream_t s) {
 
 // Fused row pass: u~ = sv A xt - alpha su u~ and s += A^T u~ (astrometric, instrumental,
 // global), then the instrumental/global reduction and the attitude pass (s += A_att^T u~).
-template <typename VT>
+// The fused row pass (u-step of the forward solve, or with TRANS the v-step of the adjoint
+// solve with its pending z/w update in ww/zz), then the instrumental/global block sums and
+// the attitude columns of s from the t-ordered copy.  Sum-of-squares partials go to `parts`.
+template <typename VT, bool TRANS = false>
 void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u, double* s_acc,
-                  hipStream_t s, const IterEvents* ev) {
+                  double* parts, hipStream_t s, const IterEvents* ev, double* ww = nullptr,
+                  double* zz = nullptr) {
     const Geo& g = h->g;
-    if (ev) mark(ev->a1_begin, s);
-    hipLaunchKernelGGL((k_aprod12<VT, 2>), dim3(h->G12), dim3(1024), h->lds12_bytes, s, g, vals,
-                       h->star, h->att, h->instr, h->xt, u, s_acc, h->st, h->partA, h->part_ig,
-                       h->chunk12, h->lds12_x);
-    if (ev) mark(ev->a1_end, s);
-    if (ev) mark(ev->a2_begin, s);
+    if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
+    hipLaunchKernelGGL((k_aprod12<VT, 2, TRANS>), dim3(h->G12), dim3(1024), h->lds12_bytes, s, g,
+                       vals, h->star, h->att, h->instr, h->xt, u, s_acc, h->st, parts,
+                       h->part_ig, h->chunk12, h->lds12_x, ww, zz);
+    if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
+    if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
     launch_reduce(h, h->G12, s_acc, 1, s);
     hipLaunchKernelGGL((k_aprod2_att<VT, A2_LSQR>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
                        h->rowT, h->tT, u, s_acc, h->st, h->chunk2t);
-    if (ev) mark(ev->a2_end, s);
+    if (ev) mark(TRANS ? ev->a1_end : ev->a2_end, s);
 }
 
 template <typename VT>
@@ -317,7 +321,7 @@ void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* a
     const Geo& g = h->g;
     if (h->fused) {
         // one read of every row: beta u = A (p o v) - alpha u and s = A^T u~ (unnormalized)
-        launch_fused<VT>(h, vals, attT, w.u, h->s, s, ev);
+        launch_fused<VT>(h, vals, attT, w.u, h->s, h->partA, s, ev);
         hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G12);
     } else {
         // beta u = A (p o v) - alpha u        (xt = p o v~ from the previous vector step)
@@ -342,6 +346,17 @@ void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* a
 void trans_iteration(const gsr_handle* h, LsqrWork& w, hipStream_t s,
                      const IterEvents* ev = nullptr) {
     const Geo& g = h->g;
+    if (h->fused) {
+        // beta u = D A^T v - alpha u  (s = A^T v~ left by the previous row pass)
+        hipLaunchKernelGGL(k_vec_tu, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, h->p64, w.u,
+                           h->xt, h->st, h->partA);
+        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn);
+        // one read of every row: pending z/w update, alpha v = A D u - beta v, s = A^T v~
+        launch_fused<double, true>(h, h->vals, h->attT64, w.v, h->s, h->partB, s, ev, w.w, w.z);
+        hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->G12,
+                           h->partB + h->G12, h->G12);
+        return;
+    }
     // beta u = D A^T v - alpha u
     if (ev) mark(ev->a2_begin, s);
     launch_aprod2<double, A2_LSQR_T>(h, h->vals, h->attT64, w.v, h->s, s);
@@ -524,11 +539,18 @@ gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_
                        w.u, h->xt, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn,
                        o.itnlim, o.fixed_iters, o.atol, o.btol);
-    // alpha_1 v_1 = A D u_1
-    launch_aprod1<double, A1_LSQR_T>(h, h->vals, h->xt, w.v, nullptr, s);
     fill(w.w, g.m, 0.0, s);
     fill(w.z, g.m, 0.0, s);
-    hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+    // alpha_1 v_1 = A D u_1 (and, fused, s = A^T v~_1 for the first u-step)
+    if (h->fused) {
+        fill(h->s, g.n, 0.0, s);
+        launch_fused<double, true>(h, h->vals, h->attT64, w.v, h->s, h->partB, s, nullptr, w.w,
+                                   w.z);
+        hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->G12);
+    } else {
+        launch_aprod1<double, A1_LSQR_T>(h, h->vals, h->xt, w.v, nullptr, s);
+        hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+    }
     ProfileOut prof;
     if (o.profile)
         GSR_TRY(run_profiled(
