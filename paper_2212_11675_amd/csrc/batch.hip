@@ -1084,7 +1084,7 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
             hipLaunchKernelGGL(k_bkeys_to_t, dim3(grid_for(M, 256, 4096)), dim3(256), 0, s, M,
                                keys_out, tbits, b->tT);
             const int64_t total = M * kAxes * kParAxis;
-            hipLaunchKernelGGL(k_gather_att<double>, dim3(grid_for(total, 256, 8192)), dim3(256),
+            hipLaunchKernelGGL(k_gather_att_rows<double>, dim3(grid_for(total, 256, 8192)), dim3(256),
                                0, s, M, vals, b->rowT, b->attT);
             e = hipStreamSynchronize(s);
         }

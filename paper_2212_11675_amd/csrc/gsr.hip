@@ -138,6 +138,11 @@ struct gsr_handle {
     // fused row pass (aprod 1 + star-ordered part of aprod 2), used when n_instr fits LDS
     int fused = 0, G12 = 1, chunk12 = 16, lds12_x = 0;
     size_t lds12_bytes = 0;
+    // row tiles of the fused pass (coefficients per precision, packed indices)
+    int64_t ntiles = 0;
+    double* tiles64 = nullptr;
+    float* tiles32 = nullptr;
+    int32_t* itiles = nullptr;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
     double *dx = nullptr, *r = nullptr;  // refinement
     hipStream_t cap = nullptr;     // capture stream
@@ -253,7 +258,8 @@ gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
     const int64_t m = g.m;
     GSR_TRY(dalloc(&h->rowT, m));
     GSR_TRY(dalloc(&h->tT, m));
-    GSR_TRY(dalloc(&h->attT64, m * kAxes * kParAxis));
+    const int64_t ntiles_att = (m + kStepRows - 1) / kStepRows;
+    GSR_TRY(dalloc(&h->attT64, ntiles_att * kTileAtt));
     if (m == 0) return GSR_OK;
     if (m > (int64_t)INT32_MAX) return fail(GSR_E_UNSUPPORTED, "more than 2^31-1 rows");
     int32_t* iota = nullptr;
@@ -271,9 +277,9 @@ gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
         e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, h->att, h->tT, iota, h->rowT,
                                                (int)m, 0, end_bit, s);
     if (e == hipSuccess) {
-        const int64_t total = m * kAxes * kParAxis;
+        const int64_t total = ntiles_att * kTileAtt;
         hipLaunchKernelGGL(k_gather_att<double>, dim3(grid_for(total, kBlock, 8192)),
-                           dim3(kBlock), 0, s, m, h->vals, h->rowT, h->attT64);
+                           dim3(kBlock), 0, s, m, ntiles_att, h->vals, h->rowT, h->attT64);
         e = hipStreamSynchronize(s);
     }
     dfree(temp);
@@ -298,6 +304,9 @@ void mark(hipEvent_t e, hipStream_t s) {
 // The fused row pass (u-step of the forward solve, or with TRANS the v-step of the adjoint
 // solve with its pending z/w update in ww/zz), then the instrumental/global block sums and
 // the attitude columns of s from the t-ordered copy.  Sum-of-squares partials go to `parts`.
+const double* tiles_of(const gsr_handle* h, const double*) { return h->tiles64; }
+const float* tiles_of(const gsr_handle* h, const float*) { return h->tiles32; }
+
 template <typename VT, bool TRANS = false>
 void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u, double* s_acc,
                   double* parts, hipStream_t s, const IterEvents* ev, double* ww = nullptr,
@@ -305,7 +314,7 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
     const Geo& g = h->g;
     if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
     hipLaunchKernelGGL((k_aprod12<VT, 2, TRANS>), dim3(h->G12), dim3(1024), h->lds12_bytes, s, g,
-                       vals, h->star, h->att, h->instr, h->xt, u, s_acc, h->st, parts,
+                       tiles_of(h, vals), h->itiles, h->star, h->xt, u, s_acc, h->st, parts,
                        h->part_ig, h->chunk12, h->lds12_x, ww, zz);
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
     if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
@@ -737,8 +746,24 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         return bail(st);
     if (n_empty && !so.allow_empty_cols)
         return bail(fail(GSR_E_LAYOUT, "%llu all-zero column(s); set allow_empty_cols", n_empty));
+    if (h->fused && g.m > 0) {
+        h->ntiles = (g.m + kStepRows - 1) / kStepRows;
+        const int64_t nv = h->ntiles * kTileVals, ni = h->ntiles * kTileIdx;
+        if ((st = dalloc(&h->tiles64, nv)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->itiles, ni)) != GSR_OK) return bail(st);
+        hipLaunchKernelGGL(k_make_tiles<double>, dim3(grid_for(nv, kBlock, 8192)), dim3(kBlock), 0,
+                           s, g.m, h->ntiles, vals, h->tiles64);
+        hipLaunchKernelGGL(k_make_itiles, dim3(grid_for(ni, kBlock, 8192)), dim3(kBlock), 0, s,
+                           g.m, h->ntiles, h->star, h->att, h->instr, h->itiles);
+        if (so.build_f32) {
+            if ((st = dalloc(&h->tiles32, nv)) != GSR_OK) return bail(st);
+            hipLaunchKernelGGL(k_make_tiles<float>, dim3(grid_for(nv, kBlock, 8192)),
+                               dim3(kBlock), 0, s, g.m, h->ntiles, vals, h->tiles32);
+        }
+    }
     if (so.build_f32) {
-        const int64_t nnz = (int64_t)g.m * kPar, natt = (int64_t)g.m * kAxes * kParAxis;
+        const int64_t nnz = (int64_t)g.m * kPar,
+                      natt = (g.m + kStepRows - 1) / kStepRows * kTileAtt;
         if ((st = dalloc(&h->vals32, nnz)) != GSR_OK) return bail(st);
         if ((st = dalloc(&h->attT32, natt)) != GSR_OK) return bail(st);
         if ((st = dalloc(&h->p32, g.n)) != GSR_OK) return bail(st);
@@ -763,6 +788,9 @@ gsr_status gsr_destroy(gsr_handle* h) {
     free_work(h->fwd32);
     free_work(h->trans);
     dfree(h->vals32);
+    dfree(h->tiles64);
+    dfree(h->tiles32);
+    dfree(h->itiles);
     dfree(h->attT32);
     dfree(h->attT64);
     dfree(h->rowT);

@@ -14,6 +14,7 @@ namespace gsr {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kPar = 24;     // coefficients per row

@@ -30,6 +30,126 @@ __device__ __forceinline__ double ld_val(const float* __restrict__ p) {
     return (double)__builtin_nontemporal_load(p);
 }
 
+// ---------------------------------------------------------------------------------------
+// Row tiles: a library-owned copy of the coefficients and indices in which every load
+// instruction of a wave step reads one contiguous block (the paper's row layout makes each
+// lane's coefficients 4 slots apart, so a wave load would touch sixteen separate 32-byte
+// pieces).  A tile holds the kStepRows rows of one wave step; lane (rg, q) needs slots
+// 4k + q (k = 0..5) of row rg:
+//   binary64 : three 1 KiB groups; group h is [rg][q][2] = slots 4(2h) + q, 4(2h+1) + q
+//   binary32 : a 1 KiB group [rg][q][4] (k = 0..3), then a 512 B group [rg][q][2] (k = 4, 5)
+//   indices  : [rg][q][2] int32 = (star, att), (instr0, instr4), (instr1, instr5),
+//              (instr2, instr3) for q = 0..3
+// Padding rows of the last tile carry zero coefficients and the last row's indices.
+constexpr int kTileVals = kStepRows * kPar;  // 384 coefficients per tile
+constexpr int kTileIdx = kStepRows * 8;      // 128 int32 per tile
+
+__device__ __forceinline__ void ld_tile(const double* __restrict__ tiles, int64_t tile, int lane,
+                                        double (&a)[6]) {
+    const f64x2* __restrict__ p = reinterpret_cast<const f64x2*>(tiles + tile * kTileVals) + lane;
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        const f64x2 v = __builtin_nontemporal_load(p + h * kWave);
+        a[2 * h] = v.x;
+        a[2 * h + 1] = v.y;
+    }
+}
+__device__ __forceinline__ void ld_tile(const float* __restrict__ tiles, int64_t tile, int lane,
+                                        double (&a)[6]) {
+    const float* __restrict__ t = tiles + tile * kTileVals;
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(t) + lane);
+    const f32x2 w = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(t + 4 * kWave) + lane);
+    a[0] = v.x;
+    a[1] = v.y;
+    a[2] = v.z;
+    a[3] = v.w;
+    a[4] = w.x;
+    a[5] = w.y;
+}
+
+// Index tile of a wave step: star, attitude start and the lane's instrumental indices
+// (ia: the instrumental slot among k = 0..5 of lane q; ib: the second one of lanes 1 and 2).
+__device__ __forceinline__ void ld_tile_idx(const int32_t* __restrict__ itiles, int64_t tile,
+                                            int lane, int32_t& sr, int32_t& tr, int32_t& ia,
+                                            int32_t& ib) {
+    const i32x2 v = __builtin_nontemporal_load(reinterpret_cast<const i32x2*>(itiles + tile * kTileIdx) + lane);
+    sr = __builtin_amdgcn_update_dpp(0, v.x, 0x00, 0xF, 0xF, false);   // quad_perm [0,0,0,0]
+    tr = __builtin_amdgcn_update_dpp(0, v.y, 0x00, 0xF, 0xF, false);
+    const int32_t i3 = __builtin_amdgcn_update_dpp(0, v.y, 0xFF, 0xF, 0xF, false);  // [3,3,3,3]
+    ia = ((lane & 3) == 0) ? i3 : v.x;
+    ib = v.y;
+}
+
+// Setup: row tiles from the paper's row layout (one thread per tile element).
+template <typename VT>
+static __global__ void k_make_tiles(int64_t m, int64_t ntiles, const double* __restrict__ vals,
+                                    VT* __restrict__ tiles) {
+    const int64_t total = ntiles * kTileVals;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t tile = e / kTileVals;
+        const int o = (int)(e - tile * kTileVals);
+        int lane, k;
+        if (sizeof(VT) == 8) {
+            lane = (o % (2 * kWave)) / 2;
+            k = 2 * (o / (2 * kWave)) + o % 2;
+        } else if (o < 4 * kWave) {
+            lane = o / 4;
+            k = o % 4;
+        } else {
+            lane = (o - 4 * kWave) / 2;
+            k = 4 + (o - 4 * kWave) % 2;
+        }
+        const int64_t row = tile * kStepRows + lane / kQuad;
+        const int slot = 4 * k + lane % kQuad;
+        tiles[e] = row < m ? (VT)vals[row * kPar + slot] : (VT)0;  // binary32: round to nearest
+    }
+}
+
+static __global__ void k_make_itiles(int64_t m, int64_t ntiles, const int32_t* __restrict__ star,
+                                     const int32_t* __restrict__ att,
+                                     const int32_t* __restrict__ instr,
+                                     int32_t* __restrict__ itiles) {
+    const int64_t total = ntiles * kTileIdx;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t tile = e / kTileIdx;
+        const int o = (int)(e - tile * kTileIdx);
+        const int lane = o / 2, h = o % 2, q = lane % kQuad;
+        const int64_t row = min(tile * kStepRows + lane / kQuad, m - 1);
+        int32_t v;
+        if (q == 0) {
+            v = h ? att[row] : star[row];
+        } else {
+            const int k = (q == 1) ? (h ? 4 : 0) : (q == 2) ? (h ? 5 : 1) : (h ? 3 : 2);
+            v = instr[row * kInstr + k];
+        }
+        itiles[e] = v;
+    }
+}
+
+// Attitude tiles (the t-ordered copy): kStepRows rows of 12 attitude coefficients; lane
+// (rg, q) needs column t + q of the three axes of row rg: a group [rg][q][2] (axes 0, 1)
+// followed by a group [rg][q] (axis 2).  Padding rows are zero.
+constexpr int kTileAtt = kStepRows * kAxes * kParAxis;  // 192 coefficients per tile
+
+__device__ __forceinline__ void ld_att_tile(const double* __restrict__ t, int64_t tile, int lane,
+                                            double (&va)[kAxes]) {
+    const double* __restrict__ b = t + tile * kTileAtt;
+    const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(b) + lane);
+    va[0] = v.x;
+    va[1] = v.y;
+    va[2] = __builtin_nontemporal_load(b + 2 * kWave + lane);
+}
+__device__ __forceinline__ void ld_att_tile(const float* __restrict__ t, int64_t tile, int lane,
+                                            double (&va)[kAxes]) {
+    const float* __restrict__ b = t + tile * kTileAtt;
+    const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(b) + lane);
+    va[0] = v.x;
+    va[1] = v.y;
+    va[2] = __builtin_nontemporal_load(b + 2 * kWave + lane);
+}
+
 // Cross-lane moves of a double with a DPP control (both 32-bit halves).
 // quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E; row_ror:4 = 0x124, row_ror:8 = 0x128.
 template <int CTRL>
@@ -368,9 +488,8 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 // Partials then are 4 rows of gridDim: sum v~^2, sum z^2, sum z w, sum w^2.
 template <typename VT, int U, bool TRANS = false>
 static __global__ __launch_bounds__(1024) void k_aprod12(
-    Geo g, const VT* __restrict__ vals, const int32_t* __restrict__ star,
-    const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
-    const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
+    Geo g, const VT* __restrict__ tiles, const int32_t* __restrict__ itiles,
+    const int32_t* __restrict__ star, const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
     const LsqrState* __restrict__ st, double* __restrict__ partials,
     double* __restrict__ part, int chunk_rows, int lds_x, double* __restrict__ ww_vec = nullptr,
     double* __restrict__ zz_vec = nullptr) {
@@ -393,8 +512,6 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     const int wpb = blockDim.x / kWave;
     const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;
     const double xglob = xx[g.glb0];
-    const int ia_off = (q == 0) ? 3 : q - 1;
-    const int ib_off = (q == 1 || q == 2) ? q + 3 : ia_off;
     const int jatt = (q + 3) & 3;
     double usq = 0.0, gacc = 0.0;
     for (int64_t ch = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks;
@@ -428,13 +545,12 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
                 const int64_t r = r0 + w * kStepRows + rg;
                 valid[w] = r < r_end;
                 const int64_t rr = valid[w] ? r : r_beg;  // in-bounds stand-in row
-                const VT* __restrict__ row = vals + rr * kPar + q;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) a[w][k] = ld_val(row + 4 * k);
-                sr[w] = star[rr];
-                tr[w] = att[rr];
-                ia[w] = instr[rr * kInstr + ia_off];
-                ib[w] = instr[rr * kInstr + ib_off];
+                // tiles past the chunk are replaced by its first one (rows of the system's
+                // last tile past m are padding inside the allocation)
+                const int64_t tile = (r0 + w * kStepRows < r_end) ? r0 / kStepRows + w
+                                                                  : r_beg / kStepRows;
+                ld_tile(tiles, tile, lane, a[w]);
+                ld_tile_idx(itiles, tile, lane, sr[w], tr[w], ia[w], ib[w]);
                 uo[w] = uu[rr];
             }
 #pragma unroll
@@ -543,9 +659,9 @@ static __global__ __launch_bounds__(256) void k_aprod2_att(
                 const int64_t kk = valid[w] ? k : k_beg;  // in-bounds stand-in
                 kt[w] = tT[kk];
                 yy[w] = (MODE == A2_SQ) ? 0.0 : ysc * y[rowT[kk]];
-                const VT* __restrict__ a = attT + kk * (kAxes * kParAxis) + q;
-#pragma unroll
-                for (int ax = 0; ax < kAxes; ++ax) va[w][ax] = ld_val(a + kParAxis * ax);
+                const int64_t tile = (k0 + w * kStepRows < k_end) ? k0 / kStepRows + w
+                                                                  : k_beg / kStepRows;
+                ld_att_tile(attT, tile, lane, va[w]);
             }
 #pragma unroll
             for (int w = 0; w < U; ++w) {
@@ -563,10 +679,28 @@ static __global__ __launch_bounds__(256) void k_aprod2_att(
     }
 }
 
-// Library-owned attitude copy in t order: attT[k][j] = vals[rowT[k]][5 + j].
+// Library-owned attitude copy in t order, as attitude tiles: row k of the copy is row
+// rowT[k] of the system; ntiles * kTileAtt elements.
 template <typename VT>
-static __global__ void k_gather_att(int64_t m, const VT* __restrict__ vals,
+static __global__ void k_gather_att(int64_t m, int64_t ntiles, const VT* __restrict__ vals,
                                     const int32_t* __restrict__ rowT, VT* __restrict__ attT) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t total = ntiles * kTileAtt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t tile = e / kTileAtt;
+        const int o = (int)(e - tile * kTileAtt);
+        const int lane = (o < 2 * kWave) ? o / 2 : o - 2 * kWave;
+        const int ax = (o < 2 * kWave) ? o % 2 : 2;
+        const int64_t k = tile * kStepRows + lane / kQuad;
+        const int j = kParAxis * ax + lane % kQuad;
+        attT[e] = k < m ? vals[(int64_t)rowT[k] * kPar + kAstro + j] : (VT)0;
+    }
+}
+
+// The same copy row by row (attT[k][j] = vals[rowT[k]][5 + j]), for the batched kernels.
+template <typename VT>
+static __global__ void k_gather_att_rows(int64_t m, const VT* __restrict__ vals,
+                                         const int32_t* __restrict__ rowT, VT* __restrict__ attT) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t total = m * (kAxes * kParAxis);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
