@@ -206,7 +206,8 @@ typedef struct gsr_batch gsr_batch;
  *   dims        host [n_sys].
  *   row_offset  host [n_sys+1]: system s owns rows row_offset[s] .. row_offset[s+1]-1 of
  *               the concatenated arrays (row_offset[0] = 0).
- *   vals/star/att/instr  device, concatenated; indices are relative to each system.
+ *   vals/star/att/instr  device, concatenated; indices are relative to each system; vals
+ *               16-byte and instr 8-byte aligned (GSR_E_INVAL otherwise).
  *   k           right-hand sides per system, 1, 2, 4 or 8 (GSR_E_UNSUPPORTED otherwise).
  * Unknowns of system s occupy columns col_offset[s] .. col_offset[s+1]-1 of the batched
  * unknown vector (gsr_batch_col_offsets), each system in the column order above.
@@ -222,7 +223,8 @@ gsr_status gsr_batch_destroy(gsr_batch *b);
 gsr_status gsr_batch_col_offsets(const gsr_batch *b, int64_t *col_offset);
 
 /* Multi-RHS products over all systems at once (RHS-minor storage, element (row, j) at
- * row*k + j):  Y[i, j] += sum A[i,c] X[c, j]  and  X[c, j] += sum A[i,c] Y[i, j]. */
+ * row*k + j):  Y[i, j] += sum A[i,c] X[c, j]  and  X[c, j] += sum A[i,c] Y[i, j].  X and Y
+ * must be 16-byte aligned (GSR_E_INVAL otherwise). */
 gsr_status gsr_batch_aprod1(gsr_batch *b, const double *X, double *Y, void *stream);
 gsr_status gsr_batch_aprod2(gsr_batch *b, const double *Y, double *X, void *stream);
 

@@ -230,6 +230,10 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
 //   U[r, j] = sv_j (A XT)[r, j] - alpha_j su_j U[r, j]
 // and S += A^T U (astrometric: run accumulators; instrumental/global: LDS of the current
 // system), reading each row once.  Sum U^2 per (block chunk, j) -> partials.
+// Lane layout: L = min(K, 4) lanes per row, each lane R = K / L right-hand sides, so one row
+// costs 16-byte loads: the row's coefficients (all L lanes read the same 192 bytes), and per
+// column the lane's R consecutive values of the K-column block (RHS-minor storage).
+// Pairs that have stopped keep their U unchanged and contribute nothing.
 template <typename VT, int K>
 static __global__ __launch_bounds__(512) void k_baprod12(
     const SysDesc* __restrict__ sys, const Seg* __restrict__ bchunks, int nbchunks,
@@ -238,8 +242,10 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     const double* __restrict__ XT, double* __restrict__ U, double* __restrict__ S,
     const LsqrState* __restrict__ st, double* __restrict__ partials, int max_instr) {
     extern __shared__ double lds[];  // [(max_instr + 1) * K] sums, then [K] block sum U^2
-    constexpr int RS = kWave / K;
-    const int lane = threadIdx.x % kWave, rr = lane / K, j = lane % K;
+    constexpr int L = K >= 4 ? 4 : K;
+    constexpr int R = K / L;
+    constexpr int RS = kWave / L;
+    const int lane = threadIdx.x % kWave, rr = lane / L, j0 = (lane % L) * R;
     const int w = threadIdx.x / kWave, wpb = blockDim.x / kWave;
     const int per = (nbchunks + gridDim.x - 1) / gridDim.x;
     const int bc_beg = blockIdx.x * per, bc_end = min(nbchunks, bc_beg + per);
@@ -249,13 +255,18 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     __syncthreads();
     int cur = -1;
     SysDesc d = {};
-    double gacc = 0.0;
-    auto flush_lds = [&]() {
-        double gs = gacc;
+    double gacc[R];
 #pragma unroll
-        for (int off = K; off < kWave; off <<= 1) gs += __shfl_xor(gs, off, kWave);
-        if (lane < K) atomicAdd(lds + d.I * K + j, gs);
-        gacc = 0.0;
+    for (int i = 0; i < R; ++i) gacc[i] = 0.0;
+    auto flush_lds = [&]() {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            double gs = gacc[i];
+#pragma unroll
+            for (int off = L; off < kWave; off <<= 1) gs += __shfl_xor(gs, off, kWave);
+            if (lane < L) atomicAdd(lds + d.I * K + j0 + i, gs);
+            gacc[i] = 0.0;
+        }
         __syncthreads();
         const int ne = (d.I + 1) * K;
         double* xi = S + (d.col0 + d.ins0) * K;  // instrumental then global: contiguous
@@ -273,9 +284,17 @@ static __global__ __launch_bounds__(512) void k_baprod12(
             cur = c.sys;
             d = sys[cur];
         }
-        const LsqrState* ps = st + (int64_t)cur * K + j;
-        const bool live = !ps->stop;
-        const double xs = ps->sv, ys = ps->alpha * ps->su;
+        bool live[R];
+        double xs[R], ys[R];
+        bool any_live = false;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const LsqrState* ps = st + (int64_t)cur * K + j0 + i;
+            live[i] = !ps->stop;
+            xs[i] = ps->sv;
+            ys[i] = ps->alpha * ps->su;
+            any_live = any_live || live[i];
+        }
         const int64_t len = c.e1 - c.e0;
         const int64_t sub = ((len + wpb - 1) / wpb + RS - 1) / RS * RS;
         const int64_t r_beg = min(c.e1, c.e0 + w * sub), r_end = min(c.e1, r_beg + sub);
@@ -285,68 +304,136 @@ static __global__ __launch_bounds__(512) void k_baprod12(
         const int32_t shared_last =
             (r_beg < r_end && r_end < sys_end && star[r_end] == star[r_end - 1]) ? star[r_end - 1]
                                                                                 : -1;
-        const double* __restrict__ Xs = XT + d.col0 * K + j;
-        double* __restrict__ Sa = S + d.col0 * K + j;
-        auto flush = [&](int32_t key, const double (&t)[kAstro]) {
-            if (rr != 0 || !live) return;
+        const double* __restrict__ Xs = XT + d.col0 * K + j0;
+        double* __restrict__ Sa = S + d.col0 * K + j0;
+        auto flush = [&](int32_t key, const double (&t)[kAstro * R]) {
+            if (rr != 0) return;
             double* xa = Sa + (int64_t)kAstro * key * K;
-            if (key == shared_first || key == shared_last) {
+            const bool shared = key == shared_first || key == shared_last;
 #pragma unroll
-                for (int q = 0; q < kAstro; ++q) atomic_add_f64(xa + q * K, t[q]);
-            } else {
+            for (int i = 0; i < R; ++i) {
+                if (!live[i]) continue;
 #pragma unroll
-                for (int q = 0; q < kAstro; ++q) xa[q * K] = t[q];  // S is zero here
+                for (int q = 0; q < kAstro; ++q) {
+                    if (shared)
+                        atomic_add_f64(xa + q * K + i, t[i * kAstro + q]);
+                    else
+                        xa[q * K + i] = t[i * kAstro + q];  // S is zero here
+                }
             }
         };
-        double acc[kAstro] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        // the lane's R values of column `col` of XT
+        auto xv = [&](int64_t col, double (&o)[R]) {
+            const double* p = Xs + col * K;
+            if constexpr (R == 2) {
+                const f64x2 t = *reinterpret_cast<const f64x2*>(p);
+                o[0] = t.x;
+                o[1] = t.y;
+            } else {
+#pragma unroll
+                for (int i = 0; i < R; ++i) o[i] = p[i];
+            }
+        };
+        double acc[kAstro * R];
+#pragma unroll
+        for (int q = 0; q < kAstro * R; ++q) acc[q] = 0.0;
         int32_t ckey = -1;
-        double usq = 0.0;
+        double usq[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) usq[i] = 0.0;
         for (int64_t r0 = r_beg; r0 < r_end; r0 += RS) {
             const int64_t r = r0 + rr;
-            const bool valid = live && r < r_end;
+            const bool valid = any_live && r < r_end;
             int32_t key = -1;
-            double v[kAstro] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (valid) {
-                const VT* __restrict__ row = vals + r * kPar;
-                double a[kPar];
+            double v[kAstro * R];
 #pragma unroll
-                for (int k = 0; k < kPar; ++k) a[k] = ld_val(row + k);
+            for (int q = 0; q < kAstro * R; ++q) v[q] = 0.0;
+            if (valid) {
+                double a[kPar];
+                if constexpr (sizeof(VT) == 8) {
+                    const f64x2* row = reinterpret_cast<const f64x2*>(vals + r * kPar);
+#pragma unroll
+                    for (int k = 0; k < kPar / 2; ++k) {
+                        const f64x2 t = __builtin_nontemporal_load(row + k);
+                        a[2 * k] = t.x;
+                        a[2 * k + 1] = t.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kPar; ++k) a[k] = ld_val(vals + r * kPar + k);
+                }
                 const int32_t sr = star[r], tr = att[r];
                 int32_t ins[kInstr];
+                const i32x2* ip = reinterpret_cast<const i32x2*>(instr + r * kInstr);
 #pragma unroll
-                for (int k = 0; k < kInstr; ++k) ins[k] = instr[r * kInstr + k];
-                double sum = 0.0;
+                for (int k = 0; k < kInstr / 2; ++k) {
+                    const i32x2 t = __builtin_nontemporal_load(ip + k);
+                    ins[2 * k] = t.x;
+                    ins[2 * k + 1] = t.y;
+                }
+                double sum[R], xv_[R];
 #pragma unroll
-                for (int k = 0; k < kAstro; ++k)
-                    sum = fma(a[k], Xs[((int64_t)kAstro * sr + k) * K], sum);
+                for (int i = 0; i < R; ++i) sum[i] = 0.0;
+                auto add = [&](double coef, int64_t col) {
+                    xv(col, xv_);
+#pragma unroll
+                    for (int i = 0; i < R; ++i) sum[i] = fma(coef, xv_[i], sum[i]);
+                };
+#pragma unroll
+                for (int k = 0; k < kAstro; ++k) add(a[k], (int64_t)kAstro * sr + k);
 #pragma unroll
                 for (int ax = 0; ax < kAxes; ++ax)
 #pragma unroll
                     for (int k = 0; k < kParAxis; ++k)
-                        sum = fma(a[kAstro + ax * kParAxis + k],
-                                  Xs[(d.att0 + (int64_t)ax * d.T + tr + k) * K], sum);
+                        add(a[kAstro + ax * kParAxis + k], d.att0 + (int64_t)ax * d.T + tr + k);
 #pragma unroll
-                for (int k = 0; k < kInstr; ++k)
-                    sum = fma(a[17 + k], Xs[(d.ins0 + ins[k]) * K], sum);
-                sum = fma(a[23], Xs[d.glb0 * K], sum);
-                double* up = U + r * K + j;
-                const double un = (ys != 0.0) ? xs * sum - ys * *up : xs * sum;
-                *up = un;
-                usq = fma(un, un, usq);
+                for (int k = 0; k < kInstr; ++k) add(a[17 + k], d.ins0 + ins[k]);
+                add(a[23], d.glb0);
+                double* up = U + r * K + j0;
+                double uo[R], un[R];
+                if constexpr (R == 2) {
+                    const f64x2 t = *reinterpret_cast<const f64x2*>(up);
+                    uo[0] = t.x;
+                    uo[1] = t.y;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) uo[i] = up[i];
+                }
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    un[i] = !live[i]       ? uo[i]
+                            : (ys[i] != 0.0) ? xs[i] * sum[i] - ys[i] * uo[i]
+                                             : xs[i] * sum[i];
+                    const double ul = live[i] ? un[i] : 0.0;
+                    usq[i] = fma(ul, ul, usq[i]);
+#pragma unroll
+                    for (int q = 0; q < kAstro; ++q) v[i * kAstro + q] = a[q] * ul;
+                    gacc[i] = fma(a[23], ul, gacc[i]);
+                }
+                if constexpr (R == 2) {
+                    *reinterpret_cast<f64x2*>(up) = f64x2{un[0], un[1]};
+                } else {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) up[i] = un[i];
+                }
                 key = sr;
 #pragma unroll
-                for (int q = 0; q < kAstro; ++q) v[q] = a[q] * un;
+                for (int k = 0; k < kInstr; ++k)
 #pragma unroll
-                for (int q = 0; q < kInstr; ++q) atomicAdd(lds + ins[q] * K + j, a[17 + q] * un);
-                gacc = fma(a[23], un, gacc);
+                    for (int i = 0; i < R; ++i)
+                        if (live[i]) atomicAdd(lds + ins[k] * K + j0 + i, a[17 + k] * un[i]);
             }
-            run_step<kAstro, K>(key, v, acc, ckey, flush);
+            run_step<kAstro * R, L>(key, v, acc, ckey, flush);
         }
-        run_close<kAstro, K>(acc, ckey, flush);
+        run_close<kAstro * R, L>(acc, ckey, flush);
         // block sum of U^2 for this block chunk
 #pragma unroll
-        for (int off = K; off < kWave; off <<= 1) usq += __shfl_xor(usq, off, kWave);
-        if (lane < K) atomicAdd(lusq + j, usq);
+        for (int i = 0; i < R; ++i) {
+            double t = usq[i];
+#pragma unroll
+            for (int off = L; off < kWave; off <<= 1) t += __shfl_xor(t, off, kWave);
+            if (lane < L) atomicAdd(lusq + j0 + i, t);
+        }
         __syncthreads();
         if (threadIdx.x < K) {
             partials[(int64_t)bc * K + threadIdx.x] = lusq[threadIdx.x];
@@ -357,57 +444,97 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     if (cur >= 0) flush_lds();
 }
 
-// Attitude pass over the t-ordered copy (each system's rows keep their own range).
+// Attitude pass over the t-ordered copy (each system's rows keep their own range).  Lane
+// layout as in k_baprod12: L = min(K, 4) lanes per row, R = K / L right-hand sides per lane;
+// each lane reads the row's 12 attitude coefficients (16-byte loads) and its R values of Y.
 template <typename VT, int MODE, int K>
 static __global__ __launch_bounds__(256) void k_baprod2_att(
     const SysDesc* __restrict__ sys, const Seg* __restrict__ chunks, int nchunks,
     const VT* __restrict__ attT, const int32_t* __restrict__ rowT,
     const int32_t* __restrict__ tT, const double* __restrict__ Y, double* __restrict__ X,
     const LsqrState* __restrict__ st) {
-    constexpr int RS = kWave / K;
+    constexpr int L = K >= 4 ? 4 : K;
+    constexpr int R = K / L;
+    constexpr int RS = kWave / L;
     constexpr int NA = kAxes * kParAxis;
-    const int lane = threadIdx.x % kWave, rr = lane / K, j = lane % K;
+    const int lane = threadIdx.x % kWave, rr = lane / L, j0 = (lane % L) * R;
     const int wpb = blockDim.x / kWave;
     for (int ch = blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks; ch += gridDim.x * wpb) {
         const Seg c = chunks[ch];
         const SysDesc d = sys[c.sys];
-        bool live = true;
-        double ysc = 1.0;
-        if (MODE == A2_LSQR) {
-            const LsqrState* p = st + (int64_t)c.sys * K + j;
-            live = !p->stop;
-            ysc = 1.0;  // u~ unnormalized; k_bvec_v applies 1/beta
+        bool live[R];
+        bool any_live = false;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            live[i] = (MODE == A2_LSQR) ? !st[(int64_t)c.sys * K + j0 + i].stop : true;
+            any_live = any_live || live[i];
         }
-        double* __restrict__ Xt = X + (d.col0 + d.att0) * K + j;
-        auto flush = [&](int32_t key, const double (&t)[NA]) {
-            if (rr != 0 || !live) return;
+        // (A2_LSQR: u~ unnormalized; k_bvec_v applies 1/beta)
+        double* __restrict__ Xt = X + (d.col0 + d.att0) * K + j0;
+        auto flush = [&](int32_t key, const double (&t)[NA * R]) {
+            if (rr != 0) return;
 #pragma unroll
-            for (int ax = 0; ax < kAxes; ++ax)
+            for (int i = 0; i < R; ++i) {
+                if (!live[i]) continue;
 #pragma unroll
-                for (int q = 0; q < kParAxis; ++q)
-                    atomic_add_f64(Xt + ((int64_t)ax * d.T + key + q) * K, t[ax * kParAxis + q]);
+                for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                    for (int q = 0; q < kParAxis; ++q)
+                        atomic_add_f64(Xt + ((int64_t)ax * d.T + key + q) * K + i,
+                                       t[i * NA + ax * kParAxis + q]);
+            }
         };
-        double acc[NA];
+        double acc[NA * R];
 #pragma unroll
-        for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+        for (int q = 0; q < NA * R; ++q) acc[q] = 0.0;
         int32_t ckey = -1;
         for (int64_t k0 = c.e0; k0 < c.e1; k0 += RS) {
             const int64_t k = k0 + rr;
-            const bool valid = live && k < c.e1;
+            const bool valid = any_live && k < c.e1;
             int32_t key = -1;
-            double v[NA];
+            double v[NA * R];
 #pragma unroll
-            for (int q = 0; q < NA; ++q) v[q] = 0.0;
+            for (int q = 0; q < NA * R; ++q) v[q] = 0.0;
             if (valid) {
                 key = tT[k];
-                const double yy = (MODE == A2_SQ) ? 0.0 : ysc * Y[(int64_t)rowT[k] * K + j];
-                const VT* __restrict__ a = attT + k * NA;
+                double yy[R];
+                if (MODE == A2_SQ) {
 #pragma unroll
-                for (int q = 0; q < NA; ++q) v[q] = contrib<MODE>(ld_val(a + q), yy);
+                    for (int i = 0; i < R; ++i) yy[i] = 0.0;
+                } else {
+                    const double* yp = Y + (int64_t)rowT[k] * K + j0;
+                    if constexpr (R == 2) {
+                        const f64x2 t = *reinterpret_cast<const f64x2*>(yp);
+                        yy[0] = t.x;
+                        yy[1] = t.y;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < R; ++i) yy[i] = yp[i];
+                    }
+#pragma unroll
+                    for (int i = 0; i < R; ++i) yy[i] = live[i] ? yy[i] : 0.0;
+                }
+                double a[NA];
+                if constexpr (sizeof(VT) == 8) {
+                    const f64x2* ap = reinterpret_cast<const f64x2*>(attT + k * NA);
+#pragma unroll
+                    for (int q = 0; q < NA / 2; ++q) {
+                        const f64x2 t = __builtin_nontemporal_load(ap + q);
+                        a[2 * q] = t.x;
+                        a[2 * q + 1] = t.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NA; ++q) a[q] = ld_val(attT + k * NA + q);
+                }
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+#pragma unroll
+                    for (int q = 0; q < NA; ++q) v[i * NA + q] = contrib<MODE>(a[q], yy[i]);
             }
-            run_step<NA, K>(key, v, acc, ckey, flush);
+            run_step<NA * R, L>(key, v, acc, ckey, flush);
         }
-        run_close<NA, K>(acc, ckey, flush);
+        run_close<NA * R, L>(acc, ckey, flush);
     }
 }
 
@@ -971,6 +1098,8 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
     const int64_t M = row_offset[n_sys];
     if (M > (int64_t)INT32_MAX) return fail(GSR_E_UNSUPPORTED, "more than 2^31-1 rows");
     if (M > 0 && (!vals || !star || !att || !instr)) return fail(GSR_E_INVAL, "null matrix array");
+    if (((uintptr_t)vals & 15) || ((uintptr_t)instr & 7))
+        return fail(GSR_E_INVAL, "vals must be 16-byte and instr 8-byte aligned");
     if ((size_t)(max_instr + 1) * k * sizeof(double) > 64 * 1024)
         return fail(GSR_E_UNSUPPORTED, "n_instr * k too large for the batched LDS accumulator");
     gsr_setup_opts so = {0, 1, 0, 0};
@@ -1136,6 +1265,7 @@ gsr_status gsr_batch_col_offsets(const gsr_batch* b, int64_t* col_offset) {
 
 gsr_status gsr_batch_aprod1(gsr_batch* b, const double* X, double* Y, void* stream) {
     if (!b || !X || !Y) return fail(GSR_E_INVAL, "null argument");
+    if (((uintptr_t)X | (uintptr_t)Y) & 15) return fail(GSR_E_INVAL, "X and Y must be 16-byte aligned");
     HIP_TRY(hipSetDevice(b->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     with_k(b->k, [&](auto kc) { blaunch_aprod1<A1_ADD, decltype(kc)::value>(b, X, Y, nullptr, s); });
@@ -1145,6 +1275,7 @@ gsr_status gsr_batch_aprod1(gsr_batch* b, const double* X, double* Y, void* stre
 
 gsr_status gsr_batch_aprod2(gsr_batch* b, const double* Y, double* X, void* stream) {
     if (!b || !X || !Y) return fail(GSR_E_INVAL, "null argument");
+    if (((uintptr_t)X | (uintptr_t)Y) & 15) return fail(GSR_E_INVAL, "X and Y must be 16-byte aligned");
     HIP_TRY(hipSetDevice(b->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     with_k(b->k, [&](auto kc) { blaunch_aprod2<A2_ADD, decltype(kc)::value>(b, Y, X, s); });

@@ -304,6 +304,7 @@ void mark(hipEvent_t e, hipStream_t s) {
 // The fused row pass (u-step of the forward solve, or with TRANS the v-step of the adjoint
 // solve with its pending z/w update in ww/zz), then the instrumental/global block sums and
 // the attitude columns of s from the t-ordered copy.  Sum-of-squares partials go to `parts`.
+constexpr int kU12 = 1;  // row steps per load batch of the fused pass (measured best)
 const double* tiles_of(const gsr_handle* h, const double*) { return h->tiles64; }
 const float* tiles_of(const gsr_handle* h, const float*) { return h->tiles32; }
 
@@ -313,8 +314,8 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
                   double* zz = nullptr) {
     const Geo& g = h->g;
     if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
-    hipLaunchKernelGGL((k_aprod12<VT, 2, TRANS>), dim3(h->G12), dim3(1024), h->lds12_bytes, s, g,
-                       tiles_of(h, vals), h->itiles, h->star, h->xt, u, s_acc, h->st, parts,
+    hipLaunchKernelGGL((k_aprod12<VT, kU12, TRANS>), dim3(h->G12), dim3(1024), h->lds12_bytes, s,
+                       g, tiles_of(h, vals), h->itiles, h->star, h->xt, u, s_acc, h->st, parts,
                        h->part_ig, h->chunk12, h->lds12_x, ww, zz);
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
     if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
@@ -695,7 +696,7 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
             const size_t lds_max = 160 * 1024;
             h->lds12_x = sizeof(double) * (2 * (size_t)g.I + 1) <= lds_max;
             h->lds12_bytes = sizeof(double) * ((size_t)g.I + 1 + (h->lds12_x ? g.I : 0));
-            const int o12 = occ((const void*)k_aprod12<double, 2>, 1024, h->lds12_bytes);
+            const int o12 = occ((const void*)k_aprod12<double, kU12>, 1024, h->lds12_bytes);
             h->chunk12 = chunk_for(o12 * n_cu * 1024 / kWave);
             h->G12 = grid(o12, 1024, h->chunk12);
         }

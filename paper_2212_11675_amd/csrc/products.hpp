@@ -480,7 +480,7 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 // s is accumulated unnormalized (1/beta is applied by the vector step once beta is known);
 // the attitude columns of s come from k_aprod2_att on the t-ordered copy.  Block partials:
 // sum u~^2 -> partials[block], instrumental/global sums -> part[block][n_instr + 1].
-// U row steps are loaded before any of them is reduced (memory-level parallelism).
+// U row steps are loaded before any of them is reduced.
 //
 // TRANS: the same pass for the transposed operator D A^T (the adjoint solve), where the
 // row-space vector is v~:  v~[r] = su (A xt)[r] - beta sv v~[r]  (xt = p o u~), preceded on
