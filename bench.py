@@ -68,6 +68,118 @@ def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
                       f"{t2 - t0:.1f} s of CPU work)"}
 
 
+# ---- HBM traffic from rocprofv3 counters ---------------------------------------------
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are taken in two separate rocprofv3 --pmc runs
+# of `bench.py --copy-calibration ...`; both counters are scaled by what they read for the
+# plain 1 GiB device copy of the same run.  The summary records a hash of the kernel sources:
+# once the kernels change, the stored traffic no longer applies and is reported as null.
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_KERNEL_SOURCES = ("paper_2212_11675_amd/csrc/kernels.hpp", "paper_2212_11675_amd/csrc/products.hpp",
+                   "paper_2212_11675_amd/csrc/gsr.hip")
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in _KERNEL_SOURCES:
+        with open(os.path.join(_HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(kernel: str, workload: str) -> str:
+    return os.path.join(_HERE, "profiles", f"{kernel}_{workload}_hbm_traffic.txt")
+
+
+def _pmc_rows(d: str, counter: str) -> list:
+    """(dispatch id, kernel name, value) of every dispatch, in dispatch order."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+                    rows.append((int(r["Dispatch_Id"]), name, float(r["Counter_Value"])))
+    return sorted(rows)
+
+
+def _pmc_means(d: str, counter: str) -> dict:
+    """Mean per dispatch for every kernel; "copy" = the first three device copies of the run
+    (the 1 GiB calibration copies, the process's first GPU work)."""
+    rows = _pmc_rows(d, counter)
+    by: dict = {}
+    for _, name, v in rows:
+        by.setdefault(name, []).append(v)
+    out = {k: sum(v) / len(v) for k, v in by.items()}
+    cal = [v for _, name, v in rows if name.startswith("__amd_rocclr_copyBuffer")][:3]
+    if len(cal) == 3:
+        out["copy"] = sum(cal) / 3
+    return out
+
+
+def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, cmd: str) -> str:
+    """Write the traffic summary of `kernel` (name prefix) from the two counter runs."""
+    fetch, write = _pmc_means(fetch_dir, "FETCH_SIZE"), _pmc_means(write_dir, "WRITE_SIZE")
+
+    def pick(tab, prefix):
+        keys = [k for k in tab if k.startswith(prefix)]
+        if not keys:
+            raise SystemExit(f"no dispatches of {prefix} in the counter output")
+        return tab[keys[0]], keys[0]
+
+    cf, _ = pick(fetch, "copy")
+    cw, _ = pick(write, "copy")
+    kf, full = pick(fetch, "gsr::" + kernel)
+    kw, _ = pick(write, "gsr::" + kernel)
+    sf, sw = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+    fb, wb = kf * 1024 * sf, kw * 1024 * sw
+    lines = [
+        f"# HBM traffic of {full}, workload {workload}",
+        f"# commands (FETCH_SIZE, then WRITE_SIZE): {cmd}",
+        "# counters are KiB per dispatch (mean over the run's dispatches); each is scaled by the",
+        "# ratio of the true 1 GiB read (written) by the calibration copy to what the counter read",
+        f"kernel: {kernel}",
+        f"workload: {workload}",
+        f"source_hash: {kernel_source_hash()}",
+        f"copy_fetch_kib: {cf:.1f}",
+        f"copy_write_kib: {cw:.1f}",
+        f"fetch_scale: {sf:.4f}",
+        f"write_scale: {sw:.4f}",
+        f"kernel_fetch_kib: {kf:.1f}",
+        f"kernel_write_kib: {kw:.1f}",
+        f"fetch_bytes_per_launch: {fb:.0f}",
+        f"write_bytes_per_launch: {wb:.0f}",
+        f"traffic_bytes_per_launch: {fb + wb:.0f}",
+    ]
+    out = traffic_path(kernel, workload)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
+
+
+def stored_traffic(kernel: str, workload: str, algorithmic: float):
+    """Traffic bytes per launch from the committed summary, or None if absent, stale, or below
+    the kernel's algorithmic bytes (then the counters missed part of the traffic)."""
+    p = traffic_path(kernel, workload)
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    with open(p) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    traffic = float(kv["traffic_bytes_per_launch"])
+    return traffic if traffic >= 0.95 * algorithmic else None
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -287,6 +399,9 @@ def main() -> None:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "CMD"),
+                    help="write profiles/<KERNEL>_<workload>_hbm_traffic.txt from two rocprofv3 "
+                         "--pmc outputs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--no-events", action="store_true",
                     help="replay the captured iteration graph instead of event-bracketed launches")
     args = ap.parse_args()
@@ -295,6 +410,10 @@ def main() -> None:
               "multi-GPU split of the path is a design note, not a measured configuration",
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_summary:
+        fd, wd, kern, cmd = args.pmc_summary
+        print(pmc_summary(fd, wd, kern, args.workload, cmd))
+        return
     if args.copy_calibration:
         import torch
 
@@ -318,11 +437,15 @@ def main() -> None:
 
     shape = synth.WORKLOADS[args.workload]
     t_gen = time.perf_counter()
-    sysd = synth.system(shape)
-    d = sysd["dims"]
-    m, n = d["n_rows"], shape.n_cols
     dev = torch.device("cuda:0")
-    t = {k: torch.from_numpy(sysd[k]).to(dev) for k in ("vals", "star", "att", "instr")}
+    if args.no_cpu_baseline:  # host copy not needed: generate and upload in row chunks
+        sysd = None
+        t, d = upload_system(shape)
+    else:
+        sysd = synth.system(shape)
+        d = sysd["dims"]
+        t = {k: torch.from_numpy(sysd[k]).to(dev) for k in ("vals", "star", "att", "instr")}
+    m, n = d["n_rows"], shape.n_cols
     x_true = torch.from_numpy(synth.x_true(shape)).to(dev)
     noise = torch.from_numpy(synth.noise(shape)).to(dev)
     torch.cuda.synchronize()
@@ -372,7 +495,9 @@ def main() -> None:
         dom = 0 if ms1 >= ms2 else 1
         gb, msd = (gbps1, ms1) if dom == 0 else (gbps2, ms2)
         roofline = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBPS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBPS, 4),
+                    "traffic": stored_traffic(names[dom], shape.name,
+                                              pb["pass1" if dom == 0 else "pass2"]),
                     "kernel": names[dom], "ms_per_launch": round(msd, 4),
                     "algorithmic_bytes_per_launch": pb["pass1" if dom == 0 else "pass2"]}
         ab = algorithmic_bytes(m, n)
