@@ -46,6 +46,15 @@ struct Seg {
 };
 
 constexpr int kBTile = 2048;  // columns per tile
+constexpr int kXcd = 8;       // accelerator dies; the dispatcher places block i on die i % 8
+
+// Block index renumbered so that the blocks of one die are consecutive: contiguous work
+// ranges (one or a few systems) then stay on one die and share its L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int per = G / kXcd, rem = G % kXcd;
+    const int x = b % kXcd, i = b / kXcd;
+    return x * per + min(x, rem) + i;
+}
 
 // ---------------------------------------------------------------------------------------
 // products
@@ -132,7 +141,7 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
     const int lane = threadIdx.x % kWave, rr = lane / K, j = lane % K;
     const int w = threadIdx.x / kWave, wpb = blockDim.x / kWave;
     const int per = (nbchunks + gridDim.x - 1) / gridDim.x;
-    const int bc_beg = blockIdx.x * per, bc_end = min(nbchunks, bc_beg + per);
+    const int bc_beg = xcd_block(blockIdx.x, gridDim.x) * per, bc_end = min(nbchunks, bc_beg + per);
     const int nl = (max_instr + 1) * K;
     for (int e = threadIdx.x; e < nl; e += blockDim.x) lds[e] = 0.0;
     __syncthreads();
@@ -226,6 +235,32 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
     if (cur >= 0) flush_lds();
 }
 
+// R consecutive doubles (16-byte pieces when R is even; p then 16-byte aligned).
+template <int R>
+__device__ __forceinline__ void ld_r(const double* __restrict__ p, double (&o)[R]) {
+    if constexpr (R % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < R; i += 2) {
+            const f64x2 t = *reinterpret_cast<const f64x2*>(p + i);
+            o[i] = t.x;
+            o[i + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) o[i] = p[i];
+    }
+}
+template <int R>
+__device__ __forceinline__ void st_r(double* __restrict__ p, const double (&v)[R]) {
+    if constexpr (R % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < R; i += 2) *reinterpret_cast<f64x2*>(p + i) = f64x2{v[i], v[i + 1]};
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) p[i] = v[i];
+    }
+}
+
 // Fused batched row pass: for every (row, rhs j) of a block chunk
 //   U[r, j] = sv_j (A XT)[r, j] - alpha_j su_j U[r, j]
 // and S += A^T U (astrometric: run accumulators; instrumental/global: LDS of the current
@@ -248,7 +283,7 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     const int lane = threadIdx.x % kWave, rr = lane / L, j0 = (lane % L) * R;
     const int w = threadIdx.x / kWave, wpb = blockDim.x / kWave;
     const int per = (nbchunks + gridDim.x - 1) / gridDim.x;
-    const int bc_beg = blockIdx.x * per, bc_end = min(nbchunks, bc_beg + per);
+    const int bc_beg = xcd_block(blockIdx.x, gridDim.x) * per, bc_end = min(nbchunks, bc_beg + per);
     const int nl = (max_instr + 1) * K;
     double* lusq = lds + nl;
     for (int e = threadIdx.x; e < nl + K; e += blockDim.x) lds[e] = 0.0;
@@ -323,17 +358,7 @@ static __global__ __launch_bounds__(512) void k_baprod12(
             }
         };
         // the lane's R values of column `col` of XT
-        auto xv = [&](int64_t col, double (&o)[R]) {
-            const double* p = Xs + col * K;
-            if constexpr (R == 2) {
-                const f64x2 t = *reinterpret_cast<const f64x2*>(p);
-                o[0] = t.x;
-                o[1] = t.y;
-            } else {
-#pragma unroll
-                for (int i = 0; i < R; ++i) o[i] = p[i];
-            }
-        };
+        auto xv = [&](int64_t col, double (&o)[R]) { ld_r<R>(Xs + col * K, o); };
         double acc[kAstro * R];
 #pragma unroll
         for (int q = 0; q < kAstro * R; ++q) acc[q] = 0.0;
@@ -391,14 +416,7 @@ static __global__ __launch_bounds__(512) void k_baprod12(
                 add(a[23], d.glb0);
                 double* up = U + r * K + j0;
                 double uo[R], un[R];
-                if constexpr (R == 2) {
-                    const f64x2 t = *reinterpret_cast<const f64x2*>(up);
-                    uo[0] = t.x;
-                    uo[1] = t.y;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < R; ++i) uo[i] = up[i];
-                }
+                ld_r<R>(up, uo);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     un[i] = !live[i]       ? uo[i]
@@ -410,12 +428,7 @@ static __global__ __launch_bounds__(512) void k_baprod12(
                     for (int q = 0; q < kAstro; ++q) v[i * kAstro + q] = a[q] * ul;
                     gacc[i] = fma(a[23], ul, gacc[i]);
                 }
-                if constexpr (R == 2) {
-                    *reinterpret_cast<f64x2*>(up) = f64x2{un[0], un[1]};
-                } else {
-#pragma unroll
-                    for (int i = 0; i < R; ++i) up[i] = un[i];
-                }
+                st_r<R>(up, un);
                 key = sr;
 #pragma unroll
                 for (int k = 0; k < kInstr; ++k)
@@ -502,15 +515,7 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
 #pragma unroll
                     for (int i = 0; i < R; ++i) yy[i] = 0.0;
                 } else {
-                    const double* yp = Y + (int64_t)rowT[k] * K + j0;
-                    if constexpr (R == 2) {
-                        const f64x2 t = *reinterpret_cast<const f64x2*>(yp);
-                        yy[0] = t.x;
-                        yy[1] = t.y;
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < R; ++i) yy[i] = yp[i];
-                    }
+                    ld_r<R>(Y + (int64_t)rowT[k] * K + j0, yy);
 #pragma unroll
                     for (int i = 0; i < R; ++i) yy[i] = live[i] ? yy[i] : 0.0;
                 }

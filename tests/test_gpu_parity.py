@@ -178,6 +178,38 @@ def test_transposed_fixed_iterations_vs_oracle(cfg_small):
         assert rel(host(lam), lamo) <= 1e-10, k
 
 
+def test_unfused_path_large_instrumental_section():
+    """n_instr above what one block's LDS holds: the separate aprod 1 / aprod 2 kernels (global
+    atomics for the instrumental columns) run instead of the fused row pass."""
+    shape = synth.Shape(700, 20, 20, 60, 11000, seed=61, name="instr11000")
+    sysd = synth.system(shape)
+    S = oracle_system(sysd)
+    h, _ = open_system(sysd, allow_empty_cols=True)
+    b = S.aprod1(synth.x_true(shape)) + synth.noise(shape)
+    for k in (1, 5, 20):
+        x = torch.empty(S.n, dtype=torch.float64, device="cuda")
+        info = gsr.gsr_lsqr_solve(h, cuda(b), x, gsr.solve_opts(itnlim=k, fixed_iters=True))
+        assert info["fused"] == 0
+        xo, io = S.lsqr(b, itnlim=k, fixed=True)
+        assert info["itn"] == io["itn"] == k
+        assert rel(host(x), xo) <= 1e-10, k
+    g = np.random.default_rng(62).standard_normal(S.n)
+    mu = torch.empty(S.m, dtype=torch.float64, device="cuda")
+    lam = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_lsqr_solve_adjoint(h, cuda(g), mu, lam, gsr.solve_opts(itnlim=6, fixed_iters=True))
+    muo, _ = S.lsqr_transposed(g, itnlim=6, fixed=True)
+    assert rel(host(mu), muo) <= 1e-10
+    h.close()
+    # the small systems take the fused pass
+    small = synth.system(SMALL_SHAPES[2])
+    h2, _ = open_system(small, allow_empty_cols=True)
+    S2 = oracle_system(small)
+    x2 = torch.empty(S2.n, dtype=torch.float64, device="cuda")
+    info = gsr.gsr_lsqr_solve(h2, cuda(np.ones(S2.m)), x2, gsr.solve_opts(itnlim=2))
+    assert info["fused"] == 1
+    h2.close()
+
+
 def test_layout_errors_and_edge_cases():
     shape = synth.Shape(20, 10, 10, 12, 30, seed=51)
     sysd = synth.system(shape)
