@@ -134,6 +134,10 @@ const char *gsr_last_error(void);
  *   opts   host, may be NULL (defaults: no f32 copy, validate, reject empty columns).
  *   out    host; receives the handle.
  * Computes the preconditioner p_j = 1/||A e_j||_2 (0 for an all-zero column) on the device.
+ * Ownership: the four arrays stay the caller's and must stay allocated and unchanged while
+ * the handle lives; the library also builds its own copies of them at setup (coefficient and
+ * index tiles, a copy ordered by attitude start, binary32 copies), so a change made after
+ * setup would reach only some of the products.  Set up a new handle instead.
  * Synchronizes `stream`.  Errors: GSR_E_INVAL, GSR_E_LAYOUT, GSR_E_NOMEM, GSR_E_HIP,
  * GSR_E_NODEVICE.
  */

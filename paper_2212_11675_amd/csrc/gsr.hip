@@ -136,7 +136,7 @@ struct gsr_handle {
     int lds1 = 0, lds2 = 0;           // instrumental columns staged / privatized in LDS
     size_t lds1_bytes = 0, lds2_bytes = 0;
     // fused row pass (aprod 1 + star-ordered part of aprod 2), used when n_instr fits LDS
-    int fused = 0, G12 = 1, chunk12 = 16, lds12_x = 0;
+    int fused = 0, G12 = 1, chunk12 = 16;
     size_t lds12_bytes = 0;
     // row tiles of the fused pass (coefficients per precision, packed indices)
     int64_t ntiles = 0;
@@ -202,13 +202,27 @@ constexpr int kBlock1 = 512;   // aprod 1
 constexpr int kBlock2s = 512;  // aprod 2, star-ordered pass
 constexpr int kBlock2t = 256;  // aprod 2, attitude pass
 
-// y (op)= A xx
+const double* tiles_of(const gsr_handle* h, const double*) { return h->tiles64; }
+const float* tiles_of(const gsr_handle* h, const float*) { return h->tiles32; }
+
+// y (op)= A xx, from the row tiles when the library built them for this precision
 template <typename VT, int MODE>
 void launch_aprod1(const gsr_handle* h, const VT* vals, const double* xx, double* y,
                    const double* b, hipStream_t s) {
-    hipLaunchKernelGGL((k_aprod1<VT, MODE>), dim3(h->G1), dim3(kBlock1), h->lds1_bytes, s, h->g,
-                       vals, h->star, h->att, h->instr, xx, y, b, h->st, h->partA, h->chunk1,
-                       h->lds1);
+    const VT* tiles = tiles_of(h, vals);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(h->G1), dim3(kBlock1), h->lds1_bytes, s, h->g, vals,
+                           h->star, h->att, h->instr, tiles, h->itiles, xx, y, b, h->st,
+                           h->partA, h->chunk1);
+    };
+    if (tiles && h->lds1)
+        go(k_aprod1<VT, MODE, true, true>);
+    else if (tiles)
+        go(k_aprod1<VT, MODE, true, false>);
+    else if (h->lds1)
+        go(k_aprod1<VT, MODE, false, true>);
+    else
+        go(k_aprod1<VT, MODE, false, false>);
 }
 
 // x[ins0 .. glb0] += the blocks' instrumental/global sums in part_ig
@@ -305,9 +319,6 @@ void mark(hipEvent_t e, hipStream_t s) {
 // solve with its pending z/w update in ww/zz), then the instrumental/global block sums and
 // the attitude columns of s from the t-ordered copy.  Sum-of-squares partials go to `parts`.
 constexpr int kU12 = 1;  // row steps per load batch of the fused pass (measured best)
-const double* tiles_of(const gsr_handle* h, const double*) { return h->tiles64; }
-const float* tiles_of(const gsr_handle* h, const float*) { return h->tiles32; }
-
 template <typename VT, bool TRANS = false>
 void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u, double* s_acc,
                   double* parts, hipStream_t s, const IterEvents* ev, double* ww = nullptr,
@@ -316,7 +327,7 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
     if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
     hipLaunchKernelGGL((k_aprod12<VT, kU12, TRANS>), dim3(h->G12), dim3(1024), h->lds12_bytes, s,
                        g, tiles_of(h, vals), h->itiles, h->star, h->xt, u, s_acc, h->st, parts,
-                       h->part_ig, h->chunk12, h->lds12_x, ww, zz);
+                       h->part_ig, h->chunk12, ww, zz);
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
     if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
     launch_reduce(h, h->G12, s_acc, 1, s);
@@ -682,7 +693,7 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
             const int64_t need = (chunks + threads / kWave - 1) / (threads / kWave);
             return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * n_cu));
         };
-        const int o1 = occ((const void*)k_aprod1<double, A1_LSQR>, kBlock1, h->lds1_bytes);
+        const int o1 = occ((const void*)k_aprod1<double, A1_LSQR, false, true>, kBlock1, h->lds1_bytes);
         const int o2s = occ((const void*)k_aprod2_star<double, A2_LSQR>, kBlock2s, h->lds2_bytes);
         const int o2t = occ((const void*)k_aprod2_att<double, A2_LSQR>, kBlock2t, 0);
         h->chunk1 = chunk_for(o1 * n_cu * kBlock1 / kWave);
@@ -691,11 +702,11 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         h->G1 = grid(o1, kBlock1, h->chunk1);
         h->G2s = grid(o2s, kBlock2s, h->chunk2s);
         h->G2t = grid(o2t, kBlock2t, h->chunk2t);
-        h->fused = h->lds2;
+        // the fused pass keeps the block's instrumental sums and the instrumental part of xt
+        // in LDS (160 KiB per CU)
+        h->lds12_bytes = sizeof(double) * (2 * (size_t)g.I + 1);
+        h->fused = h->lds2 && h->lds12_bytes <= 160 * 1024;
         if (h->fused) {
-            const size_t lds_max = 160 * 1024;
-            h->lds12_x = sizeof(double) * (2 * (size_t)g.I + 1) <= lds_max;
-            h->lds12_bytes = sizeof(double) * ((size_t)g.I + 1 + (h->lds12_x ? g.I : 0));
             const int o12 = occ((const void*)k_aprod12<double, kU12>, 1024, h->lds12_bytes);
             h->chunk12 = chunk_for(o12 * n_cu * 1024 / kWave);
             h->G12 = grid(o12, 1024, h->chunk12);

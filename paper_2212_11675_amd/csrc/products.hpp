@@ -255,17 +255,18 @@ __device__ __forceinline__ void seg_scan_rows(int32_t key, double (&v)[NV], int 
 //   A1_LSQR  : y[i] = xs sum_i - ys y[i]  with (xs, ys) = (sv, alpha su)   [forward operator]
 //   A1_LSQR_T: same with (xs, ys) = (su, beta sv)                           [transposed]
 //   A1_RESID : y[i] = b[i] - sum_i
-// LSQR modes also write the block partial of sum y[i]^2.  The instrumental part of xx is
-// staged in LDS when `lds_instr` is set (dynamic LDS of n_instr doubles).
+// LSQR modes also write the block partial of sum y[i]^2.  LDSI: the instrumental part of xx
+// is staged in LDS (dynamic LDS of n_instr doubles).  TILED: coefficients and indices come
+// from the row tiles (vals, star, att, instr then unused).
 enum { A1_ADD = 0, A1_LSQR = 1, A1_LSQR_T = 2, A1_RESID = 3 };
 
-template <typename VT, int MODE>
+template <typename VT, int MODE, bool TILED, bool LDSI>
 static __global__ __launch_bounds__(512) void k_aprod1(
     Geo g, const VT* __restrict__ vals, const int32_t* __restrict__ star,
     const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
+    const VT* __restrict__ tiles, const int32_t* __restrict__ itiles,
     const double* __restrict__ xx, double* __restrict__ y, const double* __restrict__ b,
-    const LsqrState* __restrict__ st, double* __restrict__ partials, int chunk_rows,
-    int lds_instr) {
+    const LsqrState* __restrict__ st, double* __restrict__ partials, int chunk_rows) {
     extern __shared__ double lxi[];
     __shared__ double sh[512 / kWave];
     constexpr bool kLsqr = (MODE == A1_LSQR || MODE == A1_LSQR_T);
@@ -280,11 +281,11 @@ static __global__ __launch_bounds__(512) void k_aprod1(
             ys = st->beta * st->sv;
         }
     }
-    if (lds_instr) {
+    if (LDSI) {
         for (int k = threadIdx.x; k < g.I; k += blockDim.x) lxi[k] = xx[g.ins0 + k];
         __syncthreads();
     }
-    const double* __restrict__ xi = lds_instr ? lxi : xx + g.ins0;
+    const double* __restrict__ xi = LDSI ? lxi : xx + g.ins0;
     const int lane = threadIdx.x % kWave, rg = lane / kQuad, q = lane % kQuad;
     const int wpb = blockDim.x / kWave;
     const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;
@@ -300,14 +301,21 @@ static __global__ __launch_bounds__(512) void k_aprod1(
             const int64_t r = r0 + rg;
             const bool valid = r < r_end;
             double sum = 0.0;
-            if (valid) {
+            double a[6];
+            int32_t s, t, ia, ib;
+            if (TILED) {  // the whole step's tile (rows past m are padding inside it)
+                ld_tile(tiles, r0 / kStepRows, lane, a);
+                ld_tile_idx(itiles, r0 / kStepRows, lane, s, t, ia, ib);
+            } else if (valid) {
                 const VT* __restrict__ row = vals + r * kPar + q;
-                double a[6];
 #pragma unroll
                 for (int k = 0; k < 6; ++k) a[k] = ld_val(row + 4 * k);
-                const int32_t s = star[r], t = att[r];
-                const int32_t ia = instr[r * kInstr + ia_off];
-                const int32_t ib = instr[r * kInstr + ib_off];
+                s = star[r];
+                t = att[r];
+                ia = instr[r * kInstr + ia_off];
+                ib = instr[r * kInstr + ib_off];
+            }
+            if (valid) {
                 const int64_t ca = (int64_t)kAstro * s;
                 sum = a[0] * xx[ca + q];
                 if (q == 0) sum = fma(a[1], xx[ca + 4], sum);
@@ -491,9 +499,9 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     Geo g, const VT* __restrict__ tiles, const int32_t* __restrict__ itiles,
     const int32_t* __restrict__ star, const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
     const LsqrState* __restrict__ st, double* __restrict__ partials,
-    double* __restrict__ part, int chunk_rows, int lds_x, double* __restrict__ ww_vec = nullptr,
+    double* __restrict__ part, int chunk_rows, double* __restrict__ ww_vec = nullptr,
     double* __restrict__ zz_vec = nullptr) {
-    extern __shared__ double lds[];  // [n_instr + 1] sums, then [n_instr] staged xt (lds_x)
+    extern __shared__ double lds[];  // [n_instr + 1] sums, then [n_instr] staged xt
     __shared__ double sh[1024 / kWave];
     if (st->stop) return;
     const double xs = TRANS ? st->su : st->sv;
@@ -504,10 +512,9 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     double* lsum = lds;  // instrumental and global sums of the block
     double* lxi = lds + g.I + 1;
     for (int k = threadIdx.x; k <= g.I; k += blockDim.x) lsum[k] = 0.0;
-    if (lds_x)
-        for (int k = threadIdx.x; k < g.I; k += blockDim.x) lxi[k] = xx[g.ins0 + k];
+    for (int k = threadIdx.x; k < g.I; k += blockDim.x) lxi[k] = xx[g.ins0 + k];
     __syncthreads();
-    const double* __restrict__ xi = lds_x ? lxi : xx + g.ins0;
+    const double* __restrict__ xi = lxi;  // LDS reads (not flat loads tied to vmcnt)
     const int lane = threadIdx.x % kWave, rg = lane / kQuad, q = lane % kQuad;
     const int wpb = blockDim.x / kWave;
     const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;

@@ -86,10 +86,22 @@ def test_batched_solve_matches_solo_oracle(k, iters):
             xo, io = S.lsqr(B[r0:r1, j], itnlim=iters, fixed=True)
             assert infos[s * k + j]["itn"] == io["itn"], (s, j)
             assert rel(Xg[c0:c1, j], xo) <= 1e-10, (s, j)
-    # a second solve through the cached graph gives the same answer
+    # a second solve into new buffers (graph captured again) gives the same answer
+    Bd = cuda(B.ravel())
     Xd2 = torch.empty_like(Xd)
-    gsr.gsr_batch_solve(b, cuda(B.ravel()), Xd2, gsr.solve_opts(itnlim=iters, fixed_iters=True))
-    assert rel(host(Xd2), host(Xd)) <= 1e-13
+    gsr.gsr_batch_solve(b, Bd, Xd2, gsr.solve_opts(itnlim=iters, fixed_iters=True))
+    first = host(Xd2)
+    assert rel(first, host(Xd)) <= 1e-13
+    # replays of the cached graph (same buffers), with eager work of the library and of torch
+    # on the same stream in between: every replay matches
+    rng = np.random.default_rng(90 + iters)
+    for rep in range(3):
+        Yd = cuda(rng.standard_normal(b.m * k))
+        gsr.gsr_batch_aprod1(b, cuda(rng.standard_normal(b.n * k)), Yd)
+        Xd2.mul_(-3.0).add_(Yd.sum())
+        torch.cuda.synchronize()
+        gsr.gsr_batch_solve(b, Bd, Xd2, gsr.solve_opts(itnlim=iters, fixed_iters=True))
+        assert rel(host(Xd2), first) <= 1e-13, rep
     b.close()
 
 
