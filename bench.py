@@ -264,6 +264,14 @@ def form_precision(args) -> dict:
                      "total_iterations": info["itn"], "rel_err": err}
             break
     log(f"binary32+refinement: {cfg32}, {best32}")
+    # per-iteration pass times of both precisions (events around each pass)
+    passes = {}
+    for name, prec in (("f64", gsr.GSR_F64), ("f32_values", gsr.GSR_F32V)):
+        info = timed(gsr.solve_opts(itnlim=10, fixed_iters=True, precision=prec, max_refine=1,
+                                    profile=True))[1]
+        passes[name] = {"pass1_ms": round(info["ms_pass1"], 4),
+                        "pass2_ms": round(info["ms_pass2"], 4)}
+    log(f"per-iteration passes: {passes}")
     h.close()
     return {
         "metric": "time to 1e-8 relative solution error (binary64 vs binary32-stored + refined)",
@@ -278,6 +286,7 @@ def form_precision(args) -> dict:
         "f32_refined": {"seconds": best32, **(cfg32 or {})},
         "pre_refinement_rel_err": pre,
         "reference_iterations": ref["itn"],
+        "passes_per_iteration": passes,
     }
 
 

@@ -145,6 +145,8 @@ struct gsr_handle {
     int32_t* itiles = nullptr;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
     double *dx = nullptr, *r = nullptr;  // refinement
+    double* ref_part = nullptr;          // [2 Gn] device partial norms of the refinement step
+    double* ref_host = nullptr;          // [2 Gn] pinned host copy
     hipStream_t cap = nullptr;     // capture stream
 };
 
@@ -319,13 +321,14 @@ void mark(hipEvent_t e, hipStream_t s) {
 // solve with its pending z/w update in ww/zz), then the instrumental/global block sums and
 // the attitude columns of s from the t-ordered copy.  Sum-of-squares partials go to `parts`.
 constexpr int kU12 = 1;  // row steps per load batch of the fused pass (measured best)
-template <typename VT, bool TRANS = false>
+template <typename VT, bool TRANS = false, bool INIT = false>
 void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u, double* s_acc,
                   double* parts, hipStream_t s, const IterEvents* ev, double* ww = nullptr,
                   double* zz = nullptr) {
     const Geo& g = h->g;
     if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
-    hipLaunchKernelGGL((k_aprod12<VT, kU12, TRANS>), dim3(h->G12), dim3(1024), h->lds12_bytes, s,
+    hipLaunchKernelGGL((k_aprod12<VT, kU12, TRANS, INIT>), dim3(h->G12), dim3(1024),
+                       h->lds12_bytes, s,
                        g, tiles_of(h, vals), h->itiles, h->star, h->xt, u, s_acc, h->st, parts,
                        h->part_ig, h->chunk12, ww, zz);
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
@@ -529,7 +532,10 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
                        o.itnlim, o.fixed_iters, o.atol, o.btol);
     // alpha_1 v_1 = p o A^T u_1  (the initial aprod 2)
     fill(h->s, g.n, 0.0, s);
-    launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
+    if (h->fused)
+        launch_fused<VT, false, true>(h, vals, attT, w.u, h->s, h->partB, s, nullptr);
+    else
+        launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
     hipLaunchKernelGGL(k_vec_v<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
                        w.z, h->xt, h->st, h->partB);
     hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
@@ -817,6 +823,8 @@ gsr_status gsr_destroy(gsr_handle* h) {
     dfree(h->st);
     dfree(h->dx);
     dfree(h->r);
+    dfree(h->ref_part);
+    if (h->ref_host) (void)hipHostFree(h->ref_host);
     if (h->st_host) (void)hipHostFree(h->st_host);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
@@ -901,17 +909,16 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
     if (!h->r) GSR_TRY(dalloc(&h->r, g.m));
     HIP_TRY(hipMemcpyAsync(h->r, b, sizeof(double) * g.m, hipMemcpyDeviceToDevice, s));
     fill(x, g.n, 0.0, s);
+    if (!h->ref_part) GSR_TRY(dalloc(&h->ref_part, 2 * (size_t)h->Gn));
+    if (!h->ref_host)
+        HIP_TRY(hipHostMalloc((void**)&h->ref_host, 2 * sizeof(double) * h->Gn,
+                              hipHostMallocDefault));
     int total_itn = 0, k = 0;
     gsr_solve_info inner = {};
-    double* part = nullptr;
-    GSR_TRY(dalloc(&part, 2 * (size_t)h->Gn));
+    double* part = h->ref_part;
+    double* hp = h->ref_host;
     double sums[2] = {0, 0};
-    double* hp = nullptr;
-    hipError_t e = hipHostMalloc((void**)&hp, 2 * sizeof(double) * h->Gn, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        dfree(part);
-        return hip_fail(e, "hipHostMalloc");
-    }
+    hipError_t e = hipSuccess;
     gsr_status rc = GSR_OK;
     while (k < o.max_refine) {
         rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx, o, &inner,
@@ -935,8 +942,6 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
         if (k < o.max_refine)
             launch_aprod1<double, A1_RESID>(h, h->vals, x, h->r, b, s);
     }
-    dfree(part);
-    (void)hipHostFree(hp);
     if (rc != GSR_OK) return rc;
     if (info) {
         *info = inner;

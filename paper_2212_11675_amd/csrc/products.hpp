@@ -494,7 +494,10 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 // row-space vector is v~:  v~[r] = su (A xt)[r] - beta sv v~[r]  (xt = p o u~), preceded on
 // the same rows by the pending update z += f1 w; w = sv v~ - f2 w of the row-space z, w.
 // Partials then are 4 rows of gridDim: sum v~^2, sum z^2, sum z w, sum w^2.
-template <typename VT, int U, bool TRANS = false>
+//
+// INIT: the initial aprod 2 of a solve: u~ is left as it is (no dot products) and only
+// s += A^T u~ is scattered (star-ordered columns; the attitude pass follows as usual).
+template <typename VT, int U, bool TRANS = false, bool INIT = false>
 static __global__ __launch_bounds__(1024) void k_aprod12(
     Geo g, const VT* __restrict__ tiles, const int32_t* __restrict__ itiles,
     const int32_t* __restrict__ star, const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
@@ -512,13 +515,14 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     double* lsum = lds;  // instrumental and global sums of the block
     double* lxi = lds + g.I + 1;
     for (int k = threadIdx.x; k <= g.I; k += blockDim.x) lsum[k] = 0.0;
-    for (int k = threadIdx.x; k < g.I; k += blockDim.x) lxi[k] = xx[g.ins0 + k];
+    if (!INIT)
+        for (int k = threadIdx.x; k < g.I; k += blockDim.x) lxi[k] = xx[g.ins0 + k];
     __syncthreads();
     const double* __restrict__ xi = lxi;  // LDS reads (not flat loads tied to vmcnt)
     const int lane = threadIdx.x % kWave, rg = lane / kQuad, q = lane % kQuad;
     const int wpb = blockDim.x / kWave;
     const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;
-    const double xglob = xx[g.glb0];
+    const double xglob = INIT ? 0.0 : xx[g.glb0];
     const int jatt = (q + 3) & 3;
     double usq = 0.0, gacc = 0.0;
     for (int64_t ch = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks;
@@ -563,26 +567,29 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
 #pragma unroll
             for (int w = 0; w < U; ++w) {
                 const int64_t r = r0 + w * kStepRows + rg;
-                // aprod 1 part: the row's dot product, spread over the quad
-                const int64_t ca = (int64_t)kAstro * sr[w];
-                double sum = a[w][0] * xx[ca + q];
-                if (q == 0) sum = fma(a[w][1], xx[ca + 4], sum);
-                const double* __restrict__ xa = xx + g.att0 + tr[w] + jatt;
-#pragma unroll
-                for (int ax = 0; ax < kAxes; ++ax) {
-                    const double c = (q == 0) ? a[w][ax + 2] : a[w][ax + 1];
-                    sum = fma(c, xa[(int64_t)ax * g.T], sum);
-                }
                 const double regA = (q == 0) ? a[w][5] : a[w][4];
-                sum = fma(regA, xi[ia[w]], sum);
-                if (q == 1 || q == 2) sum = fma(a[w][5], xi[ib[w]], sum);
-                if (q == 3) sum = fma(a[w][5], xglob, sum);
-                sum = quad_sum(sum);
-                const double un = (ys != 0.0) ? xs * sum - ys * uo[w] : xs * sum;
+                double un = uo[w];
+                if (!INIT) {
+                    // aprod 1 part: the row's dot product, spread over the quad
+                    const int64_t ca = (int64_t)kAstro * sr[w];
+                    double sum = a[w][0] * xx[ca + q];
+                    if (q == 0) sum = fma(a[w][1], xx[ca + 4], sum);
+                    const double* __restrict__ xa = xx + g.att0 + tr[w] + jatt;
+#pragma unroll
+                    for (int ax = 0; ax < kAxes; ++ax) {
+                        const double c = (q == 0) ? a[w][ax + 2] : a[w][ax + 1];
+                        sum = fma(c, xa[(int64_t)ax * g.T], sum);
+                    }
+                    sum = fma(regA, xi[ia[w]], sum);
+                    if (q == 1 || q == 2) sum = fma(a[w][5], xi[ib[w]], sum);
+                    if (q == 3) sum = fma(a[w][5], xglob, sum);
+                    sum = quad_sum(sum);
+                    un = (ys != 0.0) ? xs * sum - ys * uo[w] : xs * sum;
+                }
                 int32_t key = -1;
                 double v[2] = {0.0, 0.0};
                 if (valid[w]) {
-                    if (q == 0) {
+                    if (q == 0 && !INIT) {
                         if (TRANS && pending) {  // z, w updated with the old v~ of this row
                             const double wo = ww_vec[r];
                             const double zn = fma(f1, wo, zz_vec[r]);
