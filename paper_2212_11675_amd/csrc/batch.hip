@@ -38,6 +38,7 @@ struct SysDesc {
     int32_t chunk0, nchunk;    // row chunks of the system
     int32_t tile0, ntile;      // column tiles of the system
     int32_t bchunk0, nbchunk;  // block chunks of the system
+    int64_t btile0;            // first row tile of the system (rows padded to whole tiles)
 };
 
 struct Seg {
@@ -235,6 +236,56 @@ static __global__ __launch_bounds__(512) void k_baprod2_star(
     if (cur >= 0) flush_lds();
 }
 
+// Batched row tiles: per system, kStepRows consecutive rows; every lane of a row needs all
+// of the row's coefficients, so a tile is [12 pairs][16 rows][2] (one 256-byte block per
+// load instruction) and the index tile [16 rows][8] = (star, att, instr0..5).
+constexpr int kBTileVals = kStepRows * kPar;  // 384 doubles
+constexpr int kBTileIdx = kStepRows * 8;      // 128 int32
+
+static __global__ void k_make_btiles(int64_t m, int64_t ntiles, const double* __restrict__ vals,
+                                     const int32_t* __restrict__ star,
+                                     const int32_t* __restrict__ att,
+                                     const int32_t* __restrict__ instr, double* __restrict__ vt,
+                                     int32_t* __restrict__ it) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * kBTileVals;
+         e += stride) {
+        const int64_t tile = e / kBTileVals;
+        const int o = (int)(e - tile * kBTileVals);
+        const int pair = o / (2 * kStepRows), rg = (o / 2) % kStepRows, h = o % 2;
+        const int64_t row = tile * kStepRows + rg;
+        vt[e] = row < m ? vals[row * kPar + 2 * pair + h] : 0.0;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * kBTileIdx;
+         e += stride) {
+        const int64_t tile = e / kBTileIdx;
+        const int o = (int)(e - tile * kBTileIdx);
+        const int rg = o / 8, c = o % 8;
+        const int64_t row = min(tile * kStepRows + rg, m - 1);
+        it[e] = c == 0 ? star[row] : c == 1 ? att[row] : instr[row * kInstr + c - 2];
+    }
+}
+
+// Attitude tiles of the t-ordered copy, per system as the row tiles: [6 pairs][16 rows][2]
+// holding the 12 attitude coefficients of t-ordered rows row0 + 16 tile + rg (global row
+// numbers in rowT).
+constexpr int kBTileAtt = kStepRows * kAxes * kParAxis;  // 192 doubles
+
+static __global__ void k_make_batt_tiles(int64_t m, int64_t ntiles, int64_t row0,
+                                         const double* __restrict__ vals,
+                                         const int32_t* __restrict__ rowT,
+                                         double* __restrict__ at) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * kBTileAtt;
+         e += stride) {
+        const int64_t tile = e / kBTileAtt;
+        const int o = (int)(e - tile * kBTileAtt);
+        const int pair = o / (2 * kStepRows), rg = (o / 2) % kStepRows, h = o % 2;
+        const int64_t lr = tile * kStepRows + rg;
+        at[e] = lr < m ? vals[(int64_t)rowT[row0 + lr] * kPar + kAstro + 2 * pair + h] : 0.0;
+    }
+}
+
 // R consecutive doubles (16-byte pieces when R is even; p then 16-byte aligned).
 template <int R>
 __device__ __forceinline__ void ld_r(const double* __restrict__ p, double (&o)[R]) {
@@ -272,8 +323,8 @@ __device__ __forceinline__ void st_r(double* __restrict__ p, const double (&v)[R
 template <typename VT, int K>
 static __global__ __launch_bounds__(512) void k_baprod12(
     const SysDesc* __restrict__ sys, const Seg* __restrict__ bchunks, int nbchunks,
-    const VT* __restrict__ vals, const int32_t* __restrict__ star,
-    const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
+    const double* __restrict__ vt, const int32_t* __restrict__ it,
+    const int32_t* __restrict__ star,
     const double* __restrict__ XT, double* __restrict__ U, double* __restrict__ S,
     const LsqrState* __restrict__ st, double* __restrict__ partials, int max_instr) {
     extern __shared__ double lds[];  // [(max_instr + 1) * K] sums, then [K] block sum U^2
@@ -374,28 +425,24 @@ static __global__ __launch_bounds__(512) void k_baprod12(
 #pragma unroll
             for (int q = 0; q < kAstro * R; ++q) v[q] = 0.0;
             if (valid) {
+                // the row's tile (the system's rows are padded to whole tiles)
+                const int64_t lr = r - d.row0;
+                const int64_t tile = d.btile0 + lr / kStepRows;
+                const int rgl = (int)(lr % kStepRows);
                 double a[kPar];
-                if constexpr (sizeof(VT) == 8) {
-                    const f64x2* row = reinterpret_cast<const f64x2*>(vals + r * kPar);
+                const f64x2* vp = reinterpret_cast<const f64x2*>(vt + tile * kBTileVals) + rgl;
 #pragma unroll
-                    for (int k = 0; k < kPar / 2; ++k) {
-                        const f64x2 t = __builtin_nontemporal_load(row + k);
-                        a[2 * k] = t.x;
-                        a[2 * k + 1] = t.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kPar; ++k) a[k] = ld_val(vals + r * kPar + k);
+                for (int k = 0; k < kPar / 2; ++k) {
+                    const f64x2 t = __builtin_nontemporal_load(vp + k * kStepRows);
+                    a[2 * k] = t.x;
+                    a[2 * k + 1] = t.y;
                 }
-                const int32_t sr = star[r], tr = att[r];
-                int32_t ins[kInstr];
-                const i32x2* ip = reinterpret_cast<const i32x2*>(instr + r * kInstr);
-#pragma unroll
-                for (int k = 0; k < kInstr / 2; ++k) {
-                    const i32x2 t = __builtin_nontemporal_load(ip + k);
-                    ins[2 * k] = t.x;
-                    ins[2 * k + 1] = t.y;
-                }
+                typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+                const i32x4* ip = reinterpret_cast<const i32x4*>(it + tile * kBTileIdx + rgl * 8);
+                const i32x4 i0 = __builtin_nontemporal_load(ip);
+                const i32x4 i1 = __builtin_nontemporal_load(ip + 1);
+                const int32_t sr = i0.x, tr = i0.y;
+                const int32_t ins[kInstr] = {i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
                 double sum[R], xv_[R];
 #pragma unroll
                 for (int i = 0; i < R; ++i) sum[i] = 0.0;
@@ -470,6 +517,7 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
     constexpr int R = K / L;
     constexpr int RS = kWave / L;
     constexpr int NA = kAxes * kParAxis;
+    static_assert(sizeof(VT) == 8, "the batched attitude tiles are binary64");
     const int lane = threadIdx.x % kWave, rr = lane / L, j0 = (lane % L) * R;
     const int wpb = blockDim.x / kWave;
     for (int ch = blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks; ch += gridDim.x * wpb) {
@@ -520,17 +568,17 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
                     for (int i = 0; i < R; ++i) yy[i] = live[i] ? yy[i] : 0.0;
                 }
                 double a[NA];
-                if constexpr (sizeof(VT) == 8) {
-                    const f64x2* ap = reinterpret_cast<const f64x2*>(attT + k * NA);
+                {  // the row's attitude tile
+                    const int64_t lr = k - d.row0;
+                    const int64_t tile = d.btile0 + lr / kStepRows;
+                    const f64x2* ap = reinterpret_cast<const f64x2*>(attT + tile * kBTileAtt) +
+                                      (int)(lr % kStepRows);
 #pragma unroll
                     for (int q = 0; q < NA / 2; ++q) {
-                        const f64x2 t = __builtin_nontemporal_load(ap + q);
+                        const f64x2 t = __builtin_nontemporal_load(ap + q * kStepRows);
                         a[2 * q] = t.x;
                         a[2 * q + 1] = t.y;
                     }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < NA; ++q) a[q] = ld_val(attT + k * NA + q);
                 }
 #pragma unroll
                 for (int i = 0; i < R; ++i)
@@ -846,6 +894,10 @@ struct gsr_batch {
     Seg *chunks = nullptr, *bchunks = nullptr, *tiles = nullptr;
     int nchunks = 0, nbchunks = 0, ntiles = 0;
     Tuning tune;
+    // row tiles (coefficients, indices) of the fused pass
+    double* bvt = nullptr;
+    int32_t* bit = nullptr;
+    int64_t nbtiles = 0;
     // t-ordered attitude copy
     int32_t *rowT = nullptr, *tT = nullptr;
     double* attT = nullptr;
@@ -973,8 +1025,8 @@ void b_iteration(gsr_batch* b, hipStream_t s) {
     // one read of every row: U = sv A XT - alpha su U and S = A^T U (star-ordered part)
     const size_t lds = sizeof(double) * ((size_t)(b->max_instr + 1) * K + K);
     hipLaunchKernelGGL((k_baprod12<double, K>), dim3(b->G2s), dim3(b->tune.star_block), lds, s,
-                       b->d_sys, b->bchunks, b->nbchunks, b->vals, b->star, b->att, b->instr,
-                       b->XT, b->U, b->S, b->st, b->part, b->max_instr);
+                       b->d_sys, b->bchunks, b->nbchunks, b->bvt, b->bit, b->star, b->XT, b->U,
+                       b->S, b->st, b->part, b->max_instr);
     hipLaunchKernelGGL((k_baprod2_att<double, A2_LSQR, K>), dim3(b->G2t), dim3(256), 0, s,
                        b->d_sys, b->chunks, b->nchunks, b->attT, b->rowT, b->tT, b->U, b->S,
                        b->st);
@@ -1031,9 +1083,8 @@ gsr_status autotune(gsr_batch* b, hipStream_t s) {
             for (int rep = 0; rep < 3; ++rep) {
                 if (rep == 1) (void)hipEventRecord(e0, s);
                 hipLaunchKernelGGL((k_baprod12<double, K>), dim3(b->G2s), dim3(t.star_block), lds,
-                                   s, b->d_sys, b->bchunks, b->nbchunks, b->vals, b->star,
-                                   b->att, b->instr, b->XT, b->U, b->S, b->st, b->part,
-                                   b->max_instr);
+                                   s, b->d_sys, b->bchunks, b->nbchunks, b->bvt, b->bit,
+                                   b->star, b->XT, b->U, b->S, b->st, b->part, b->max_instr);
                 hipLaunchKernelGGL((k_baprod2_att<double, A2_LSQR, K>), dim3(b->G2t), dim3(256),
                                    0, s, b->d_sys, b->chunks, b->nchunks, b->attT, b->rowT,
                                    b->tT, b->U, b->S, b->st);
@@ -1144,6 +1195,8 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
         d.n_stars = dims[i].n_stars;
         d.T = g.T;
         d.I = g.I;
+        d.btile0 = b->nbtiles;
+        b->nbtiles += (d.m + kStepRows - 1) / kStepRows;
         b->col_off[i] = col;
         col += g.n;
         max_T = std::max<int64_t>(max_T, g.T);
@@ -1161,6 +1214,17 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
     if ((st = balloc(&b->XT, NK)) != GSR_OK) return bail(st);
     if ((st = balloc(&b->U, MK)) != GSR_OK) return bail(st);
     if ((st = balloc(&b->st, (size_t)n_sys * k)) != GSR_OK) return bail(st);
+    if ((st = balloc(&b->bvt, (size_t)b->nbtiles * kBTileVals)) != GSR_OK) return bail(st);
+    if ((st = balloc(&b->bit, (size_t)b->nbtiles * kBTileIdx)) != GSR_OK) return bail(st);
+    for (int i = 0; i < n_sys; ++i) {
+        const SysDesc& d = b->h_sys[i];
+        const int64_t nt = (d.m + kStepRows - 1) / kStepRows;
+        if (nt == 0) continue;
+        hipLaunchKernelGGL(k_make_btiles, dim3(grid_for(nt * kBTileVals, 256, 4096)), dim3(256), 0,
+                           s, d.m, nt, vals + d.row0 * kPar, star + d.row0, att + d.row0,
+                           instr + d.row0 * kInstr, b->bvt + d.btile0 * kBTileVals,
+                           b->bit + d.btile0 * kBTileIdx);
+    }
     b->st_host.resize((size_t)n_sys * k);
     {
         hipError_t e = hipMemsetAsync(b->st, 0, sizeof(LsqrState) * n_sys * k, s);
@@ -1191,7 +1255,7 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
     // attitude coefficients in (system, t) order
     if ((st = balloc(&b->rowT, M)) != GSR_OK) return bail(st);
     if ((st = balloc(&b->tT, M)) != GSR_OK) return bail(st);
-    if ((st = balloc(&b->attT, (size_t)M * kAxes * kParAxis)) != GSR_OK) return bail(st);
+    if ((st = balloc(&b->attT, (size_t)b->nbtiles * kBTileAtt)) != GSR_OK) return bail(st);
     if (M > 0) {
         int tbits = 1;
         while (tbits < 31 && (1LL << tbits) <= max_T) ++tbits;
@@ -1217,9 +1281,14 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_bkeys_to_t, dim3(grid_for(M, 256, 4096)), dim3(256), 0, s, M,
                                keys_out, tbits, b->tT);
-            const int64_t total = M * kAxes * kParAxis;
-            hipLaunchKernelGGL(k_gather_att_rows<double>, dim3(grid_for(total, 256, 8192)), dim3(256),
-                               0, s, M, vals, b->rowT, b->attT);
+            for (int i = 0; i < n_sys; ++i) {
+                const SysDesc& d = b->h_sys[i];
+                const int64_t nt = (d.m + kStepRows - 1) / kStepRows;
+                if (nt == 0) continue;
+                hipLaunchKernelGGL(k_make_batt_tiles, dim3(grid_for(nt * kBTileAtt, 256, 4096)),
+                                   dim3(256), 0, s, d.m, nt, d.row0, vals, b->rowT,
+                                   b->attT + d.btile0 * kBTileAtt);
+            }
             e = hipStreamSynchronize(s);
         }
         bfree(keys);
@@ -1255,7 +1324,7 @@ gsr_status gsr_batch_destroy(gsr_batch* b) {
     for (void* p : {(void*)b->d_sys, (void*)b->chunks, (void*)b->bchunks, (void*)b->tiles,
                     (void*)b->rowT, (void*)b->tT, (void*)b->attT, (void*)b->p, (void*)b->st,
                     (void*)b->U, (void*)b->V, (void*)b->W, (void*)b->Z, (void*)b->XT,
-                    (void*)b->S, (void*)b->part})
+                    (void*)b->S, (void*)b->part, (void*)b->bvt, (void*)b->bit})
         bfree(p);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;

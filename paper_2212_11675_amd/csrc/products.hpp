@@ -711,19 +711,6 @@ static __global__ void k_gather_att(int64_t m, int64_t ntiles, const VT* __restr
     }
 }
 
-// The same copy row by row (attT[k][j] = vals[rowT[k]][5 + j]), for the batched kernels.
-template <typename VT>
-static __global__ void k_gather_att_rows(int64_t m, const VT* __restrict__ vals,
-                                         const int32_t* __restrict__ rowT, VT* __restrict__ attT) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t total = m * (kAxes * kParAxis);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int64_t k = e / (kAxes * kParAxis);
-        const int j = (int)(e % (kAxes * kParAxis));
-        attT[e] = vals[(int64_t)rowT[k] * kPar + kAstro + j];
-    }
-}
-
 static __global__ void k_iota(int64_t m, int32_t* __restrict__ v) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
