@@ -327,7 +327,8 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     const int32_t* __restrict__ star,
     const double* __restrict__ XT, double* __restrict__ U, double* __restrict__ S,
     const LsqrState* __restrict__ st, double* __restrict__ partials, int max_instr) {
-    extern __shared__ double lds[];  // [(max_instr + 1) * K] sums, then [K] block sum U^2
+    // [(max_instr + 1) * K] sums, [K] block sum U^2, [max_instr * K] instrumental part of XT
+    extern __shared__ double lds[];
     constexpr int L = K >= 4 ? 4 : K;
     constexpr int R = K / L;
     constexpr int RS = kWave / L;
@@ -337,6 +338,7 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     const int bc_beg = xcd_block(blockIdx.x, gridDim.x) * per, bc_end = min(nbchunks, bc_beg + per);
     const int nl = (max_instr + 1) * K;
     double* lusq = lds + nl;
+    double* lxi = lusq + K;
     for (int e = threadIdx.x; e < nl + K; e += blockDim.x) lds[e] = 0.0;
     __syncthreads();
     int cur = -1;
@@ -369,6 +371,10 @@ static __global__ __launch_bounds__(512) void k_baprod12(
             if (cur >= 0) flush_lds();
             cur = c.sys;
             d = sys[cur];
+            // the system's instrumental columns of XT, read from LDS below
+            const double* xs_i = XT + (d.col0 + d.ins0) * K;
+            for (int e = threadIdx.x; e < d.I * K; e += blockDim.x) lxi[e] = xs_i[e];
+            __syncthreads();
         }
         bool live[R];
         double xs[R], ys[R];
@@ -459,7 +465,13 @@ static __global__ __launch_bounds__(512) void k_baprod12(
                     for (int k = 0; k < kParAxis; ++k)
                         add(a[kAstro + ax * kParAxis + k], d.att0 + (int64_t)ax * d.T + tr + k);
 #pragma unroll
-                for (int k = 0; k < kInstr; ++k) add(a[17 + k], d.ins0 + ins[k]);
+                for (int k = 0; k < kInstr; ++k) {
+                    double xl[R];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) xl[i] = lxi[ins[k] * K + j0 + i];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) sum[i] = fma(a[17 + k], xl[i], sum[i]);
+                }
                 add(a[23], d.glb0);
                 double* up = U + r * K + j0;
                 double uo[R], un[R];
@@ -1023,7 +1035,7 @@ template <int K>
 void b_iteration(gsr_batch* b, hipStream_t s) {
     const dim3 tgrid((unsigned)std::min(b->ntiles, b->n_cu * 8));
     // one read of every row: U = sv A XT - alpha su U and S = A^T U (star-ordered part)
-    const size_t lds = sizeof(double) * ((size_t)(b->max_instr + 1) * K + K);
+    const size_t lds = sizeof(double) * ((size_t)(2 * b->max_instr + 1) * K + K);
     hipLaunchKernelGGL((k_baprod12<double, K>), dim3(b->G2s), dim3(b->tune.star_block), lds, s,
                        b->d_sys, b->bchunks, b->nbchunks, b->bvt, b->bit, b->star, b->XT, b->U,
                        b->S, b->st, b->part, b->max_instr);
@@ -1079,7 +1091,7 @@ gsr_status autotune(gsr_batch* b, hipStream_t s) {
             // state is still zero here, so the values are zeros)
             HIP_TRY_VOID(hipMemsetAsync(b->XT, 0, sizeof(double) * b->N * K, s));
             HIP_TRY_VOID(hipMemsetAsync(b->U, 0, sizeof(double) * b->M * K, s));
-            const size_t lds = sizeof(double) * ((size_t)(b->max_instr + 1) * K + K);
+            const size_t lds = sizeof(double) * ((size_t)(2 * b->max_instr + 1) * K + K);
             for (int rep = 0; rep < 3; ++rep) {
                 if (rep == 1) (void)hipEventRecord(e0, s);
                 hipLaunchKernelGGL((k_baprod12<double, K>), dim3(b->G2s), dim3(t.star_block), lds,
@@ -1156,7 +1168,7 @@ gsr_status gsr_batch_setup(int32_t n_sys, const gsr_dims* dims, const int64_t* r
     if (M > 0 && (!vals || !star || !att || !instr)) return fail(GSR_E_INVAL, "null matrix array");
     if (((uintptr_t)vals & 15) || ((uintptr_t)instr & 7))
         return fail(GSR_E_INVAL, "vals must be 16-byte and instr 8-byte aligned");
-    if ((size_t)(max_instr + 1) * k * sizeof(double) > 64 * 1024)
+    if ((size_t)((2 * max_instr + 1) * k + k) * sizeof(double) > 160 * 1024)
         return fail(GSR_E_UNSUPPORTED, "n_instr * k too large for the batched LDS accumulator");
     gsr_setup_opts so = {0, 1, 0, 0};
     if (opts) so = *opts;
