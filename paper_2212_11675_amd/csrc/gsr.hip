@@ -689,8 +689,17 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
             hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
             return (e != hipSuccess || per_cu < 1) ? 1 : per_cu;
         };
+        // rows per wave chunk: at most 1024, and sized so that every wave of the persistent
+        // grid gets (nearly) the same number of chunks (small systems: at least 4 per wave)
         auto chunk_for = [&](int waves) {
-            int64_t c = g.m / (4 * (int64_t)std::max(waves, 1));
+            const int64_t w = std::max(waves, 1);
+            int64_t c;
+            if (g.m >= 4 * 1024 * w) {
+                const int64_t per = (g.m + 1024 * w - 1) / (1024 * w);  // chunks per wave
+                c = (g.m + w * per - 1) / (w * per);
+            } else {
+                c = g.m / (4 * w);
+            }
             c = std::max<int64_t>(kStepRows, std::min<int64_t>(1024, c));
             return (int)((c + kStepRows - 1) / kStepRows * kStepRows);
         };
