@@ -167,17 +167,36 @@ __device__ __forceinline__ double quad_sum(double v) {
     return v;
 }
 
-// Sum over the lanes with the same lane % STRIDE, result in all of them.
+// v[l] + v[l ^ 16] (PAIR = 16) or v[l] + v[l ^ 32] (PAIR = 32) in every lane, with the gfx950
+// row swaps (no LDS crossbar): swapping a register with itself yields, in every lane, the
+// value of the lower and of the upper partner, added in that order (the same in both lanes).
+template <int PAIR>
+__device__ __forceinline__ double pair_sum(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    unsigned l0, l1, h0, h1;
+    if (PAIR == 16) {
+        const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+    } else {
+        const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+    }
+    return __hiloint2double((int)h0, (int)l0) + __hiloint2double((int)h1, (int)l1);
+}
+
+// Sum over the lanes with the same lane % STRIDE (STRIDE = 1, 2, 4 or 8), result in all of
+// them: DPP within each 16-lane row, then the two row swaps across rows.
 template <int STRIDE>
 __device__ __forceinline__ double group_sum(double v) {
-    int off = STRIDE;
-    if (STRIDE == 4) {  // within each 16-lane row by rotation, then across rows
-        v += dpp_f64<0x128>(v);
-        v += dpp_f64<0x124>(v);
-        off = 16;
-    }
-    for (; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    static_assert(STRIDE == 1 || STRIDE == 2 || STRIDE == 4 || STRIDE == 8, "stride");
+    if (STRIDE <= 1) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    if (STRIDE <= 2) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if (STRIDE <= 4) v += dpp_f64<0x124>(v);  // row_ror:4
+    v += dpp_f64<0x128>(v);                   // row_ror:8
+    v = pair_sum<16>(v);
+    return pair_sum<32>(v);
 }
 
 // Runs of equal keys over the row groups of a wave (lane = STRIDE * group + q; keys sorted
