@@ -142,7 +142,6 @@ struct gsr_handle {
     int64_t ntiles = 0;
     double* tiles64 = nullptr;
     float* tiles32 = nullptr;
-    int32_t* itiles = nullptr;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
     double *dx = nullptr, *r = nullptr;  // refinement
     double* ref_part = nullptr;          // [2 Gn] device partial norms of the refinement step
@@ -214,7 +213,7 @@ void launch_aprod1(const gsr_handle* h, const VT* vals, const double* xx, double
     const VT* tiles = tiles_of(h, vals);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(h->G1), dim3(kBlock1), h->lds1_bytes, s, h->g, vals,
-                           h->star, h->att, h->instr, tiles, h->itiles, xx, y, b, h->st,
+                           h->star, h->att, h->instr, tiles, xx, y, b, h->st,
                            h->partA, h->chunk1);
     };
     if (tiles && h->lds1)
@@ -329,7 +328,7 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
     if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
     hipLaunchKernelGGL((k_aprod12<VT, kU12, TRANS, INIT>), dim3(h->G12), dim3(1024),
                        h->lds12_bytes, s,
-                       g, tiles_of(h, vals), h->itiles, h->star, h->xt, u, s_acc, h->st, parts,
+                       g, tiles_of(h, vals), h->star, h->xt, u, s_acc, h->st, parts,
                        h->part_ig, h->chunk12, ww, zz);
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
     if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
@@ -776,16 +775,20 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
     if (h->fused && g.m > 0) {
         h->ntiles = (g.m + kStepRows - 1) / kStepRows;
         const int64_t nv = h->ntiles * kTileVals, ni = h->ntiles * kTileIdx;
-        if ((st = dalloc(&h->tiles64, nv)) != GSR_OK) return bail(st);
-        if ((st = dalloc(&h->itiles, ni)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->tiles64, h->ntiles * tile_elems<double>())) != GSR_OK)
+            return bail(st);
         hipLaunchKernelGGL(k_make_tiles<double>, dim3(grid_for(nv, kBlock, 8192)), dim3(kBlock), 0,
                            s, g.m, h->ntiles, vals, h->tiles64);
-        hipLaunchKernelGGL(k_make_itiles, dim3(grid_for(ni, kBlock, 8192)), dim3(kBlock), 0, s,
-                           g.m, h->ntiles, h->star, h->att, h->instr, h->itiles);
+        hipLaunchKernelGGL(k_make_itiles<double>, dim3(grid_for(ni, kBlock, 8192)), dim3(kBlock),
+                           0, s, g.m, h->ntiles, h->star, h->att, h->instr, h->tiles64);
         if (so.build_f32) {
-            if ((st = dalloc(&h->tiles32, nv)) != GSR_OK) return bail(st);
+            if ((st = dalloc(&h->tiles32, h->ntiles * tile_elems<float>())) != GSR_OK)
+                return bail(st);
             hipLaunchKernelGGL(k_make_tiles<float>, dim3(grid_for(nv, kBlock, 8192)),
                                dim3(kBlock), 0, s, g.m, h->ntiles, vals, h->tiles32);
+            hipLaunchKernelGGL(k_make_itiles<float>, dim3(grid_for(ni, kBlock, 8192)),
+                               dim3(kBlock), 0, s, g.m, h->ntiles, h->star, h->att, h->instr,
+                               h->tiles32);
         }
     }
     if (so.build_f32) {
@@ -817,7 +820,6 @@ gsr_status gsr_destroy(gsr_handle* h) {
     dfree(h->vals32);
     dfree(h->tiles64);
     dfree(h->tiles32);
-    dfree(h->itiles);
     dfree(h->attT32);
     dfree(h->attT64);
     dfree(h->rowT);

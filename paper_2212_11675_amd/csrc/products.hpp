@@ -40,13 +40,19 @@ __device__ __forceinline__ double ld_val(const float* __restrict__ p) {
 //   binary32 : a 1 KiB group [rg][q][4] (k = 0..3), then a 512 B group [rg][q][2] (k = 4, 5)
 //   indices  : [rg][q][2] int32 = (star, att), (instr0, instr4), (instr1, instr5),
 //              (instr2, instr3) for q = 0..3
-// Padding rows of the last tile carry zero coefficients and the last row's indices.
+// The index tile follows the coefficients of the same tile (one stream per wave).  Padding
+// rows of the last tile carry zero coefficients and the last row's indices.
 constexpr int kTileVals = kStepRows * kPar;  // 384 coefficients per tile
 constexpr int kTileIdx = kStepRows * 8;      // 128 int32 per tile
+template <typename VT>
+constexpr int64_t tile_elems() {  // coefficients, then the index tile, in units of VT
+    return kTileVals + kTileIdx * 4 / (int64_t)sizeof(VT);
+}
 
 __device__ __forceinline__ void ld_tile(const double* __restrict__ tiles, int64_t tile, int lane,
                                         double (&a)[6]) {
-    const f64x2* __restrict__ p = reinterpret_cast<const f64x2*>(tiles + tile * kTileVals) + lane;
+    const f64x2* __restrict__ p =
+        reinterpret_cast<const f64x2*>(tiles + tile * tile_elems<double>()) + lane;
 #pragma unroll
     for (int h = 0; h < 3; ++h) {
         const f64x2 v = __builtin_nontemporal_load(p + h * kWave);
@@ -56,7 +62,7 @@ __device__ __forceinline__ void ld_tile(const double* __restrict__ tiles, int64_
 }
 __device__ __forceinline__ void ld_tile(const float* __restrict__ tiles, int64_t tile, int lane,
                                         double (&a)[6]) {
-    const float* __restrict__ t = tiles + tile * kTileVals;
+    const float* __restrict__ t = tiles + tile * tile_elems<float>();
     const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(t) + lane);
     const f32x2 w = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(t + 4 * kWave) + lane);
     a[0] = v.x;
@@ -69,10 +75,12 @@ __device__ __forceinline__ void ld_tile(const float* __restrict__ tiles, int64_t
 
 // Index tile of a wave step: star, attitude start and the lane's instrumental indices
 // (ia: the instrumental slot among k = 0..5 of lane q; ib: the second one of lanes 1 and 2).
-__device__ __forceinline__ void ld_tile_idx(const int32_t* __restrict__ itiles, int64_t tile,
-                                            int lane, int32_t& sr, int32_t& tr, int32_t& ia,
-                                            int32_t& ib) {
-    const i32x2 v = __builtin_nontemporal_load(reinterpret_cast<const i32x2*>(itiles + tile * kTileIdx) + lane);
+template <typename VT>
+__device__ __forceinline__ void ld_tile_idx(const VT* __restrict__ tiles, int64_t tile, int lane,
+                                            int32_t& sr, int32_t& tr, int32_t& ia, int32_t& ib) {
+    const int32_t* itile =
+        reinterpret_cast<const int32_t*>(tiles + tile * tile_elems<VT>() + kTileVals);
+    const i32x2 v = __builtin_nontemporal_load(reinterpret_cast<const i32x2*>(itile) + lane);
     sr = __builtin_amdgcn_update_dpp(0, v.x, 0x00, 0xF, 0xF, false);   // quad_perm [0,0,0,0]
     tr = __builtin_amdgcn_update_dpp(0, v.y, 0x00, 0xF, 0xF, false);
     const int32_t i3 = __builtin_amdgcn_update_dpp(0, v.y, 0xFF, 0xF, 0xF, false);  // [3,3,3,3]
@@ -89,6 +97,7 @@ static __global__ void k_make_tiles(int64_t m, int64_t ntiles, const double* __r
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
         const int64_t tile = e / kTileVals;
         const int o = (int)(e - tile * kTileVals);
+        VT* __restrict__ dst = tiles + tile * tile_elems<VT>() + o;
         int lane, k;
         if (sizeof(VT) == 8) {
             lane = (o % (2 * kWave)) / 2;
@@ -102,14 +111,14 @@ static __global__ void k_make_tiles(int64_t m, int64_t ntiles, const double* __r
         }
         const int64_t row = tile * kStepRows + lane / kQuad;
         const int slot = 4 * k + lane % kQuad;
-        tiles[e] = row < m ? (VT)vals[row * kPar + slot] : (VT)0;  // binary32: round to nearest
+        *dst = row < m ? (VT)vals[row * kPar + slot] : (VT)0;  // binary32: round to nearest
     }
 }
 
+template <typename VT>
 static __global__ void k_make_itiles(int64_t m, int64_t ntiles, const int32_t* __restrict__ star,
                                      const int32_t* __restrict__ att,
-                                     const int32_t* __restrict__ instr,
-                                     int32_t* __restrict__ itiles) {
+                                     const int32_t* __restrict__ instr, VT* __restrict__ tiles) {
     const int64_t total = ntiles * kTileIdx;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -124,7 +133,7 @@ static __global__ void k_make_itiles(int64_t m, int64_t ntiles, const int32_t* _
             const int k = (q == 1) ? (h ? 4 : 0) : (q == 2) ? (h ? 5 : 1) : (h ? 3 : 2);
             v = instr[row * kInstr + k];
         }
-        itiles[e] = v;
+        reinterpret_cast<int32_t*>(tiles + tile * tile_elems<VT>() + kTileVals)[o] = v;
     }
 }
 
@@ -283,8 +292,8 @@ template <typename VT, int MODE, bool TILED, bool LDSI>
 static __global__ __launch_bounds__(512) void k_aprod1(
     Geo g, const VT* __restrict__ vals, const int32_t* __restrict__ star,
     const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
-    const VT* __restrict__ tiles, const int32_t* __restrict__ itiles,
-    const double* __restrict__ xx, double* __restrict__ y, const double* __restrict__ b,
+    const VT* __restrict__ tiles, const double* __restrict__ xx, double* __restrict__ y,
+    const double* __restrict__ b,
     const LsqrState* __restrict__ st, double* __restrict__ partials, int chunk_rows) {
     extern __shared__ double lxi[];
     __shared__ double sh[512 / kWave];
@@ -324,7 +333,7 @@ static __global__ __launch_bounds__(512) void k_aprod1(
             int32_t s, t, ia, ib;
             if (TILED) {  // the whole step's tile (rows past m are padding inside it)
                 ld_tile(tiles, r0 / kStepRows, lane, a);
-                ld_tile_idx(itiles, r0 / kStepRows, lane, s, t, ia, ib);
+                ld_tile_idx(tiles, r0 / kStepRows, lane, s, t, ia, ib);
             } else if (valid) {
                 const VT* __restrict__ row = vals + r * kPar + q;
 #pragma unroll
@@ -518,8 +527,8 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 // s += A^T u~ is scattered (star-ordered columns; the attitude pass follows as usual).
 template <typename VT, int U, bool TRANS = false, bool INIT = false>
 static __global__ __launch_bounds__(1024) void k_aprod12(
-    Geo g, const VT* __restrict__ tiles, const int32_t* __restrict__ itiles,
-    const int32_t* __restrict__ star, const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
+    Geo g, const VT* __restrict__ tiles, const int32_t* __restrict__ star,
+    const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
     const LsqrState* __restrict__ st, double* __restrict__ partials,
     double* __restrict__ part, int chunk_rows, double* __restrict__ ww_vec = nullptr,
     double* __restrict__ zz_vec = nullptr) {
@@ -580,7 +589,7 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
                 const int64_t tile = (r0 + w * kStepRows < r_end) ? r0 / kStepRows + w
                                                                   : r_beg / kStepRows;
                 ld_tile(tiles, tile, lane, a[w]);
-                ld_tile_idx(itiles, tile, lane, sr[w], tr[w], ia[w], ib[w]);
+                ld_tile_idx(tiles, tile, lane, sr[w], tr[w], ia[w], ib[w]);
                 uo[w] = uu[rr];
             }
 #pragma unroll
