@@ -54,3 +54,26 @@ SMALL_SHAPES = [
     synth.Shape(300, 20, 20, 100, 50, seed=24, name="stars300_obs20"),
     synth.Shape(2000, 10, 60, 200, 500, seed=25, name="stars2000_obs10to60"),
 ]
+
+
+def upload_chunked(shape, chunk_rows: int = 10_000_000):
+    """Generate `shape` on the host in row chunks and copy it to the GPU (bounded host
+    memory); returns the device arrays, the dims and the star row pointer."""
+    rp = shape.row_ptr()
+    m = int(rp[-1])
+    dev = torch.device("cuda:0")
+    t = {"vals": torch.empty(24 * m, dtype=torch.float64, device=dev),
+         "star": torch.empty(m, dtype=torch.int32, device=dev),
+         "att": torch.empty(m, dtype=torch.int32, device=dev),
+         "instr": torch.empty(6 * m, dtype=torch.int32, device=dev)}
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        part = synth.rows(shape, r0, r1, row_ptr=rp)
+        t["vals"][24 * r0: 24 * r1].copy_(torch.from_numpy(part["vals"]))
+        t["star"][r0:r1].copy_(torch.from_numpy(part["star"]))
+        t["att"][r0:r1].copy_(torch.from_numpy(part["att"]))
+        t["instr"][6 * r0: 6 * r1].copy_(torch.from_numpy(part["instr"]))
+    torch.cuda.synchronize()
+    dims = dict(n_rows=m, n_stars=shape.n_stars, n_dfa=shape.n_dfa, n_instr=shape.n_instr,
+                n_glob=1)
+    return t, dims, rp
