@@ -1,9 +1,10 @@
 // The two products of the hot path (Section 3, Algorithms 1 and 2), written for gfx950.
 //
 // Lane layout ("quad"): four lanes per row, sixteen rows per wave step.  Lane q of a row
-// holds the coefficients in slots 4k + q (k = 0..5), so every vector load instruction of a
-// wave reads sixteen 32-byte pieces (four consecutive coefficients of sixteen rows) and
-// every attitude access of a quad covers the four consecutive columns t..t+3 of one axis:
+// holds the coefficients in slots 4k + q (k = 0..5), so every attitude access of a quad
+// covers the four consecutive columns t..t+3 of one axis.  Read from the caller's row layout
+// a wave load touches sixteen 32-byte pieces; the library's row tiles (below) turn every
+// load of a wave step into one contiguous block:
 //
 //   q = 0 : slots 0 4 8 12 16 20   astro 0, astro 4, att j=3 (axes 0,1,2), instr 3
 //   q = 1 : slots 1 5 9 13 17 21   astro 1, att j=0 (axes 0,1,2), instr 0, instr 4
@@ -11,9 +12,8 @@
 //   q = 3 : slots 3 7 11 15 19 23  astro 3, att j=2 (axes 0,1,2), instr 2, global
 //
 // Waves walk contiguous chunks of rows, so runs of equal keys (the star of a row in the
-// star-ordered pass, the attitude start t in the attitude pass) are reduced in registers
-// with a segmented scan across the 16 row groups plus a carry between steps; a run is
-// written once when it ends.
+// star-ordered pass, the attitude start t in the attitude pass) are accumulated in registers
+// (run_step) and reduced over the row groups and written once when they end.
 #pragma once
 
 #include "kernels.hpp"
@@ -258,23 +258,6 @@ __device__ __forceinline__ void run_close(double (&acc)[NV], int32_t& ckey, F&& 
     for (int j = 0; j < NV; ++j) red[j] = group_sum<STRIDE>(acc[j]);
     flush(ckey, red);
     ckey = -1;
-}
-
-// Inclusive segmented scan over the row groups of a wave (lane = STRIDE * group + q),
-// segments given by equal `key` (keys of a segment are contiguous).  NV values per lane.
-template <int NV, int STRIDE = kQuad>
-__device__ __forceinline__ void seg_scan_rows(int32_t key, double (&v)[NV], int lane) {
-#pragma unroll
-    for (int off = STRIDE; off < kWave; off <<= 1) {
-        const int32_t kk = __shfl_up(key, off, kWave);
-        double o[NV];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) o[j] = __shfl_up(v[j], off, kWave);
-        if (lane >= off && kk == key) {
-#pragma unroll
-            for (int j = 0; j < NV; ++j) v[j] += o[j];
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------------------
