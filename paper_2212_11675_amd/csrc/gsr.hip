@@ -147,9 +147,6 @@ struct gsr_handle {
     double* ref_part = nullptr;          // [2 Gn] device partial norms of the refinement step
     double* ref_host = nullptr;          // [2 Gn] pinned host copy
     hipStream_t cap = nullptr;     // capture stream
-    hipStream_t side = nullptr;    // second stream of the forward iteration (astrometric v-step)
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    int GnA = 1, GnB = 1;          // v-step grids over columns [0, att0) and [att0, n)
 };
 
 namespace {
@@ -346,35 +343,9 @@ void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* a
                    const double* p, hipStream_t s, const IterEvents* ev = nullptr) {
     const Geo& g = h->g;
     if (h->fused) {
-        // one read of every row: beta u = A (p o v) - alpha u and s = A^T u~ (unnormalized);
-        // the astrometric, instrumental and global columns of s are complete after it
-        if (ev) mark(ev->a1_begin, s);
-        hipLaunchKernelGGL((k_aprod12<VT, kU12>), dim3(h->G12), dim3(1024), h->lds12_bytes, s, g,
-                           tiles_of(h, vals), h->star, h->xt, w.u, h->s, h->st, h->partA,
-                           h->part_ig, h->chunk12);
-        if (ev) mark(ev->a1_end, s);
-        if (ev) mark(ev->a2_begin, s);
-        launch_reduce(h, h->G12, h->s, 1, s);
+        // one read of every row: beta u = A (p o v) - alpha u and s = A^T u~ (unnormalized)
+        launch_fused<VT>(h, vals, attT, w.u, h->s, h->partA, s, ev);
         hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G12);
-        // the astrometric v-step runs on the side stream while the attitude pass (bound by
-        // its random gather of u~, not by bandwidth) fills the attitude columns of s
-        (void)hipEventRecord(h->ev_fork, s);
-        (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-        hipLaunchKernelGGL(k_vec_v<false>, dim3(h->GnA), dim3(kBlock), 0, h->side, (int64_t)0,
-                           (int64_t)g.att0, h->s, p, w.v, w.w, w.z, h->xt, h->st, h->partB,
-                           h->GnA + h->GnB, 0);
-        (void)hipEventRecord(h->ev_join, h->side);
-        hipLaunchKernelGGL((k_aprod2_att<VT, A2_LSQR>), dim3(h->G2t), dim3(kBlock2t), 0, s, g,
-                           attT, h->rowT, h->tT, w.u, h->s, h->st, h->chunk2t);
-        if (ev) mark(ev->a2_end, s);
-        hipLaunchKernelGGL(k_vec_v<false>, dim3(h->GnB), dim3(kBlock), 0, s, (int64_t)g.att0,
-                           g.n, h->s, p, w.v, w.w, w.z, h->xt, h->st, h->partB,
-                           h->GnA + h->GnB, h->GnA);
-        (void)hipStreamWaitEvent(s, h->ev_join, 0);
-        const int G = h->GnA + h->GnB;
-        hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, G,
-                           h->partB + G, G);
-        return;
     } else {
         // beta u = A (p o v) - alpha u        (xt = p o v~ from the previous vector step)
         if (ev) mark(ev->a1_begin, s);
@@ -387,8 +358,8 @@ void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* a
         if (ev) mark(ev->a2_end, s);
     }
     // alpha v = p o (s / beta) - beta v, with the pending z/w update of the previous iteration
-    hipLaunchKernelGGL(k_vec_v<false>, dim3(h->Gn), dim3(kBlock), 0, s, (int64_t)0, g.n, h->s, p,
-                       w.v, w.w, w.z, h->xt, h->st, h->partB, h->Gn, 0);
+    hipLaunchKernelGGL(k_vec_v<false>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
+                       w.z, h->xt, h->st, h->partB);
     hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn,
                        h->partB + h->Gn, h->Gn);
 }
@@ -564,8 +535,8 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
         launch_fused<VT, false, true>(h, vals, attT, w.u, h->s, h->partB, s, nullptr);
     else
         launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
-    hipLaunchKernelGGL(k_vec_v<true>, dim3(h->Gn), dim3(kBlock), 0, s, (int64_t)0, g.n, h->s, p,
-                       w.v, w.w, w.z, h->xt, h->st, h->partB, h->Gn, 0);
+    hipLaunchKernelGGL(k_vec_v<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
+                       w.z, h->xt, h->st, h->partB);
     hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
     ProfileOut prof;
     if (o.profile)
@@ -706,8 +677,6 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
     // launch shapes: persistent grids sized by occupancy; row chunks of 16..1024 rows
     // so that every wave slot of the GPU gets several chunks
     h->Gn = grid_for(g.n, kBlock, kVecBlocksMax);
-    h->GnA = grid_for(g.att0, kBlock, kVecBlocksMax);
-    h->GnB = grid_for(g.n - g.att0, kBlock, kVecBlocksMax);
     h->Gm = grid_for(g.m, kBlock, kVecBlocksMax);
     h->lds1 = g.I <= kInstrLdsMax;
     h->lds2 = g.I <= kInstrLdsMax;
@@ -761,8 +730,7 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
     if ((st = dalloc(&h->p64, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->s, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->xt, g.n)) != GSR_OK) return bail(st);
-    const int part_len =
-        std::max(std::max(std::max(h->G1, h->Gm), std::max(h->Gn, h->GnA + h->GnB)), h->G12);
+    const int part_len = std::max(std::max(std::max(h->G1, h->Gm), h->Gn), h->G12);
     if ((st = dalloc(&h->partA, part_len)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->partB, 4 * (size_t)part_len)) != GSR_OK) return bail(st);
     if (h->lds2 && (st = dalloc(&h->part_ig, (size_t)std::max(h->G2s, h->G12) * (g.I + 1))) !=
@@ -775,9 +743,6 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         e = hipHostMalloc((void**)&h->st_host, sizeof(LsqrState), hipHostMallocDefault);
         if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
         e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
     }
 
@@ -873,9 +838,6 @@ gsr_status gsr_destroy(gsr_handle* h) {
     if (h->ref_host) (void)hipHostFree(h->ref_host);
     if (h->st_host) (void)hipHostFree(h->st_host);
     if (h->cap) (void)hipStreamDestroy(h->cap);
-    if (h->side) (void)hipStreamDestroy(h->side);
-    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     delete h;
     return GSR_OK;
 }

@@ -141,17 +141,13 @@ static __global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const do
 //          v~ = p o s - beta sv v~
 // s is reset to 0 and xt = p o v~ (the operand of the next aprod 1) is written.
 // Partials (4 rows of G): sum v~^2, sum z^2, sum z w, sum w^2.
-// Columns [col0, col1); block partials go to partials[q * pstride + poff + block] (q = 0..3), so
-// that two launches over disjoint column ranges can share one partial array.
 template <bool INIT>
-static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t col0, int64_t col1,
-                                                  double* __restrict__ s,
+static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __restrict__ s,
                                                   const double* __restrict__ p,
                                                   double* __restrict__ v, double* __restrict__ w,
                                                   double* __restrict__ z, double* __restrict__ xt,
                                                   const LsqrState* __restrict__ st,
-                                                  double* __restrict__ partials, int pstride,
-                                                  int poff) {
+                                                  double* __restrict__ partials) {
     __shared__ double sh[kBlock / kWave];
     if (!INIT && st->stop) return;
     const bool pending = !INIT && st->pending;
@@ -160,7 +156,7 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t col0, int64_t c
     const double su = st->su;  // s holds A^T u~ unnormalized
     double avv = 0.0, azz = 0.0, azw = 0.0, aww = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t j = col0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; j < col1; j += stride) {
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
         const double sj = s[j];
         s[j] = 0.0;
         double vn;
@@ -186,16 +182,16 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t col0, int64_t c
         xt[j] = p[j] * vn;
         avv = fma(vn, vn, avv);
     }
-    double* __restrict__ out = partials + poff + blockIdx.x;
+    const int G = gridDim.x;
     double tot = block_sum<kBlock>(avv, sh);
-    if (threadIdx.x == 0) out[0] = tot;
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
     if (!INIT) {
         tot = block_sum<kBlock>(azz, sh);
-        if (threadIdx.x == 0) out[pstride] = tot;
+        if (threadIdx.x == 0) partials[G + blockIdx.x] = tot;
         tot = block_sum<kBlock>(azw, sh);
-        if (threadIdx.x == 0) out[2 * pstride] = tot;
+        if (threadIdx.x == 0) partials[2 * G + blockIdx.x] = tot;
         tot = block_sum<kBlock>(aww, sh);
-        if (threadIdx.x == 0) out[3 * (int64_t)pstride] = tot;
+        if (threadIdx.x == 0) partials[3 * G + blockIdx.x] = tot;
     }
 }
 
