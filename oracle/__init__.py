@@ -3,8 +3,8 @@
 Thin ctypes binding of ``oracle.c``: a plain single-threaded CPU implementation
 (IEEE double) of the Gaia AVU-GSR PC-LSQR hot path -- aprod 1 / aprod 2
 (Algorithms 1 and 2 of arXiv 2212.11675), the column-norm preconditioner
-(Section 2), PC-LSQR (Section 3 flowchart; Paige & Saunders 1982), the
-mixed-precision residual correction and the adjoint gradient.
+(Section 2), PC-LSQR with its variance estimate (Section 3 flowchart; Paige & Saunders
+1982), the mixed-precision residual correction and the adjoint gradient.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library.
@@ -73,6 +73,9 @@ def _load():
         lib.or_pclsqr.restype = ctypes.c_int
         lib.or_pclsqr.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, vp,
                                   ctypes.POINTER(Info), vp]
+        lib.or_pclsqr_var.restype = ctypes.c_int
+        lib.or_pclsqr_var.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, vp, vp,
+                                      ctypes.POINTER(Info)]
         lib.or_lsqr_transposed.restype = ctypes.c_int
         lib.or_lsqr_transposed.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, vp,
                                            ctypes.POINTER(Info)]
@@ -176,6 +179,19 @@ class System:
         if hist:
             return x, info.as_dict(), h[: info.itn]
         return x, info.as_dict()
+
+    def lsqr_var(self, b, itnlim=100, fixed=True, atol=1e-14, btol=1e-14, p=None):
+        """PC-LSQR with the variance estimate: returns (x, var, info dict); var estimates
+        diag((A^T A)^-1)."""
+        b = _f64(b)
+        assert b.size == self.m
+        if p is None:
+            p = self.colnorm()
+        x, var = np.empty(self.n), np.empty(self.n)
+        info = Info()
+        _load().or_pclsqr_var(*self._args(), _p(_f64(p)), _p(b), int(itnlim), int(bool(fixed)),
+                              float(atol), float(btol), _p(x), _p(var), ctypes.byref(info))
+        return x, var, info.as_dict()
 
     def lsqr_transposed(self, g, itnlim=1000, fixed=False, atol=1e-14, btol=1e-14, p=None,
                         precond=True):

@@ -27,7 +27,11 @@
  *   - "norm of the column" is the Euclidean norm and p holds its reciprocal;
  *     an all-zero column gets p = 0;
  *   - the stopping rule is Paige & Saunders' pair of tests with atol/btol, or a
- *     fixed iteration count; an exact breakdown (alpha or beta = 0) always stops.
+ *     fixed iteration count; an exact breakdown (alpha or beta = 0) always stops;
+ *   - the variances the paper updates every iteration (Section 3, flowchart
+ *     paragraph) are Paige & Saunders' estimate of diag((A^T A)^-1): the sum over
+ *     the iterations of (w_i / rho_i)^2 in the preconditioned unknowns, multiplied
+ *     by p^2 at the end like the solution is multiplied by p.
  */
 #include <math.h>
 #include <stdint.h>
@@ -204,7 +208,7 @@ static void scal(double *v, int64_t n, double a)
  * If `hist_rnorm` is not NULL it receives phibar_{i+1} for i = 1..itn.
  */
 static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t fixed, double atol,
-                     double btol, double *z, or_info *info, double *hist_rnorm)
+                     double btol, double *z, or_info *info, double *hist_rnorm, double *var)
 {
     const int64_t m = op_rows(op), n = op_cols(op);
     double *u = malloc((size_t)m * sizeof(double));
@@ -212,6 +216,8 @@ static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t f
     double *w = malloc((size_t)n * sizeof(double));
     memcpy(u, b, (size_t)m * sizeof(double));
     memset(z, 0, (size_t)n * sizeof(double));
+    if (var)
+        memset(var, 0, (size_t)n * sizeof(double));
     memset(info, 0, sizeof *info);
 
     double beta = nrm2(u, m);
@@ -262,6 +268,10 @@ static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t f
         phibar = s * phibar;
         const double t1 = phi / rho, t2 = theta / rho;
         for (int64_t j = 0; j < n; ++j) {
+            if (var) { /* d = w / rho, var += d^2 (w before its update) */
+                const double d = w[j] / rho;
+                var[j] += d * d;
+            }
             z[j] += t1 * w[j];
             w[j] = v[j] - t2 * w[j];
         }
@@ -309,10 +319,32 @@ int or_pclsqr(const or_dims *d, const double *vals, const int32_t *star, const i
 {
     const int64_t n = or_n_cols(d);
     or_op op = {d, vals, star, att, instr, p, 0, malloc((size_t)n * sizeof(double))};
-    const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, x, info, hist_rnorm);
+    const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, x, info, hist_rnorm, NULL);
     if (p)
         for (int64_t j = 0; j < n; ++j)
             x[j] *= p[j];
+    free(op.tmp);
+    return rc;
+}
+
+/*
+ * PC-LSQR with the variance estimate: var[j] estimates diag((A^T A)^-1)_j (the
+ * preconditioned sum of (w_i / rho_i)^2 times p_j^2).  The standard error of x_j
+ * under independent residuals is sqrt(var[j]) * ||r|| / sqrt(n_rows - n_cols).
+ */
+int or_pclsqr_var(const or_dims *d, const double *vals, const int32_t *star,
+                  const int32_t *att, const int32_t *instr, const double *p, const double *b,
+                  int32_t itnlim, int32_t fixed, double atol, double btol, double *x,
+                  double *var, or_info *info)
+{
+    const int64_t n = or_n_cols(d);
+    or_op op = {d, vals, star, att, instr, p, 0, malloc((size_t)n * sizeof(double))};
+    const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, x, info, NULL, var);
+    if (p)
+        for (int64_t j = 0; j < n; ++j) {
+            x[j] *= p[j];
+            var[j] *= p[j] * p[j];
+        }
     free(op.tmp);
     return rc;
 }
@@ -332,7 +364,7 @@ int or_lsqr_transposed(const or_dims *d, const double *vals, const int32_t *star
     for (int64_t j = 0; j < n; ++j)
         rhs[j] = p ? p[j] * g[j] : g[j];
     or_op op = {d, vals, star, att, instr, p, 1, malloc((size_t)n * sizeof(double))};
-    const int rc = lsqr_core(&op, rhs, itnlim, fixed, atol, btol, mu, info, NULL);
+    const int rc = lsqr_core(&op, rhs, itnlim, fixed, atol, btol, mu, info, NULL, NULL);
     free(op.tmp);
     free(rhs);
     return rc;

@@ -3,7 +3,8 @@
 - a hand-worked placement of the 24 coefficients (tests/golden/tiny_structure.txt);
 - an independent scipy.sparse construction from the Section 3 description;
 - scipy.sparse.linalg.lsqr (a library implementation of Paige & Saunders' LSQR) for
-  the step-by-step iterates of PC-LSQR;
+  the step-by-step iterates of PC-LSQR and its variance estimate;
+- diag((A^T A)^-1) for the variance estimate after a full Krylov space;
 - dense least squares / normal equations for converged solutions;
 - invariants: adjoint identity, exact recovery of x_true, monotone residual,
   finite termination, preconditioner invariance of the converged solution;
@@ -133,6 +134,44 @@ def test_lsqr_iterates_match_scipy_lsqr(shape, ks):
         assert info["itn"] == k
         xs = _scipy_pclsqr_iterate(A, p, b, k)
         assert np.linalg.norm(x - xs) <= 1e-11 * np.linalg.norm(xs), k
+
+
+@pytest.mark.parametrize("shape,ks", [
+    (synth.Shape(4, 30, 30, 7, 9, seed=9), [1, 2, 3, 5, 8, 13]),
+    (synth.S1K_O60, [1, 2, 5, 20]),
+])
+def test_variance_estimate_matches_scipy_lsqr(shape, ks):
+    """Variance estimate: scipy's LSQR (calc_var) on A diag(p) gives the preconditioned sum of
+    (w_i / rho_i)^2 step by step; the oracle returns it times p^2."""
+    s, S = _system(shape)
+    A = csr(s["dims"], s["vals"], s["star"], s["att"], s["instr"])
+    b = A @ synth.x_true(shape) + synth.noise(shape)
+    p = S.colnorm()
+    Ab = spla.LinearOperator(A.shape, matvec=lambda z: A @ (p * z),
+                             rmatvec=lambda y: p * (A.T @ y), dtype=np.float64)
+    for k in ks:
+        x, var, info = S.lsqr_var(b, itnlim=k, fixed=True)
+        res = spla.lsqr(Ab, b, atol=0.0, btol=0.0, conlim=0.0, iter_lim=k, calc_var=True)
+        vs = p * p * res[-1]
+        assert np.linalg.norm(var - vs) <= 1e-11 * np.linalg.norm(vs), k
+        x0, _ = S.lsqr(b, itnlim=k, fixed=True)
+        assert np.array_equal(x, x0)  # the estimate does not change the iterate
+
+
+def test_variance_estimate_exact_after_n_steps():
+    """After exactly n steps (full Krylov space) the estimate is diag((A^T A)^-1) up to rounding
+    and loss of orthogonality; 29 unknowns."""
+    shape = synth.Shape(2, 30, 30, 4, 6, seed=93)
+    s, S = _system(shape)
+    A = dense(s["dims"], s["vals"], s["star"], s["att"], s["instr"])
+    assert S.n == 29
+    b = A @ synth.x_true(shape) + synth.noise(shape)
+    x, var, info = S.lsqr_var(b, itnlim=S.n, fixed=True)
+    ref = np.diag(np.linalg.inv(A.T @ A))
+    assert np.max(np.abs(var - ref) / ref) <= 1e-3
+    # far from complete after a third of the steps: the sum only grows towards the diagonal
+    _, var10, _ = S.lsqr_var(b, itnlim=10, fixed=True)
+    assert np.all(var10 <= ref * (1 + 1e-9)) and np.max(np.abs(var10 - ref) / ref) > 0.1
 
 
 def test_lsqr_converged_vs_lstsq_and_precond_invariance():
