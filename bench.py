@@ -396,6 +396,61 @@ def form_grad(args) -> dict:
     }
 
 
+def form_var(args) -> dict:
+    """PC-LSQR with the variance estimate beside the plain solve, timed alternately."""
+    import torch
+
+    import synth
+    from paper_2212_11675_amd import gsr
+
+    shape = synth.WORKLOADS[args.workload]
+    t, d = upload_system(shape)
+    dev = torch.device("cuda:0")
+    m, n = d["n_rows"], shape.n_cols
+    h = gsr.gsr_lsqr_setup(gsr.make_dims(m, d["n_stars"], d["n_dfa"], d["n_instr"]), t["vals"],
+                           t["star"], t["att"], t["instr"])
+    b = torch.from_numpy(synth.noise(shape)).to(dev)
+    gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    var = torch.empty(n, dtype=torch.float64, device=dev)
+    opts = gsr.solve_opts(itnlim=args.iters, fixed_iters=True)
+
+    def run(with_var):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if with_var:
+            info = gsr.gsr_lsqr_solve_var(h, b, x, var, opts)
+        else:
+            info = gsr.gsr_lsqr_solve(h, b, x, opts)
+        torch.cuda.synchronize()
+        return info, time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        run(False)
+        run(True)
+    tv = tp = 0.0
+    for _ in range(args.steps):
+        tp += run(False)[1]
+        info, dt = run(True)
+        tv += dt
+    it = args.steps * args.iters
+    # standard errors: sqrt(var) scaled by the residual standard deviation
+    se = var.sqrt() * (info["rnorm"] / max(m - n, 1) ** 0.5)
+    h.close()
+    return {
+        "metric": "PC-LSQR iterations per second with the variance estimate (binary64)",
+        "value": round(it / tv, 3), "unit": "iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * tv / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": shape.name, "rows": m, "cols": n,
+                   "iterations_per_step": args.iters},
+        "plain_iterations_per_s": round(it / tp, 3),
+        "overhead": round(tv / tp - 1.0, 4),
+        "median_standard_error": float(se.median()),
+    }
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,7 +458,8 @@ def main() -> None:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--workload", default="stars1e6_obs20_dfa3e4_instr6e3")
-    ap.add_argument("--form", default="f64", choices=["f64", "precision", "batch", "grad"],
+    ap.add_argument("--form", default="f64",
+                    choices=["f64", "precision", "batch", "grad", "var"],
                     help="f64: the headline binary64 solve; the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -434,7 +490,8 @@ def main() -> None:
         log("copy calibration: 3 copies of 1 GiB (1073741824 B read + written each)")
         del src, dst
     if args.form != "f64":
-        fn = {"precision": form_precision, "batch": form_batch, "grad": form_grad}[args.form]
+        fn = {"precision": form_precision, "batch": form_batch, "grad": form_grad,
+              "var": form_var}[args.form]
         print(json.dumps(fn(args)), flush=True)
         return
 

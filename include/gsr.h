@@ -185,6 +185,19 @@ gsr_status gsr_lsqr_solve(gsr_handle *h, const double *b, double *x, const gsr_s
                           gsr_solve_info *info, void *stream);
 
 /*
+ * The same binary64 PC-LSQR plus the variances the paper updates every iteration (Section 3,
+ * flowchart paragraph): Paige & Saunders' estimate of diag((A^T A)^-1), the running sum of
+ * (w_i / rho_i)^2 in the preconditioned unknowns, multiplied by p^2 at the end like the
+ * solution is multiplied by p.  var [n_cols] output (device).  The standard error of x_j
+ * under independent residuals is sqrt(var_j) * info.rnorm / sqrt(n_rows - n_cols)
+ * (n_rows > n_cols).  The estimate is complete only after a full Krylov space (n_cols
+ * steps in exact arithmetic); fewer steps give a lower bound.  opts->precision must be
+ * GSR_F64 (GSR_E_UNSUPPORTED otherwise).  Synchronizes `stream`.
+ */
+gsr_status gsr_lsqr_solve_var(gsr_handle *h, const double *b, double *x, double *var,
+                              const gsr_solve_opts *opts, gsr_solve_info *info, void *stream);
+
+/*
  * Adjoint of the least-squares solve, for a loss L(x*) with g = dL/dx* [n_cols]:
  *   mu  [n_rows] = minimum-norm solution of A^T mu = g  (LSQR on D A^T, rhs D g) = dL/db,
  *   lam [n_cols] = argmin || A lam - mu ||               (PC-LSQR)  = (A^T A)^{-1} g.

@@ -107,6 +107,7 @@ namespace {
 struct LsqrWork {
     int64_t rows = 0, cols = 0;
     double *u = nullptr, *v = nullptr, *w = nullptr, *z = nullptr;
+    double* var = nullptr;  // [cols] variance estimate (solves that return it)
     hipGraphExec_t graph = nullptr;
     int graph_iters = 0;
 };
@@ -143,6 +144,7 @@ struct gsr_handle {
     double* tiles64 = nullptr;
     float* tiles32 = nullptr;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
+    LsqrWork fwd64v;               // forward recurrence with the variance estimate
     double *dx = nullptr, *r = nullptr;  // refinement
     double* ref_part = nullptr;          // [2 Gn] device partial norms of the refinement step
     double* ref_host = nullptr;          // [2 Gn] pinned host copy
@@ -176,10 +178,11 @@ void free_work(LsqrWork& w) {
     dfree(w.v);
     dfree(w.w);
     dfree(w.z);
+    dfree(w.var);
     w = LsqrWork();
 }
 
-gsr_status ensure_work(LsqrWork& w, int64_t rows, int64_t cols) {
+gsr_status ensure_work(LsqrWork& w, int64_t rows, int64_t cols, bool with_var = false) {
     if (w.u) return GSR_OK;
     w.rows = rows;
     w.cols = cols;
@@ -187,6 +190,7 @@ gsr_status ensure_work(LsqrWork& w, int64_t rows, int64_t cols) {
     GSR_TRY(dalloc(&w.v, cols));
     GSR_TRY(dalloc(&w.w, cols));
     GSR_TRY(dalloc(&w.z, cols));
+    if (with_var) GSR_TRY(dalloc(&w.var, cols));
     return GSR_OK;
 }
 
@@ -338,7 +342,7 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
     if (ev) mark(TRANS ? ev->a1_end : ev->a2_end, s);
 }
 
-template <typename VT>
+template <typename VT, bool VAR = false>
 void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
                    const double* p, hipStream_t s, const IterEvents* ev = nullptr) {
     const Geo& g = h->g;
@@ -358,8 +362,8 @@ void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* a
         if (ev) mark(ev->a2_end, s);
     }
     // alpha v = p o (s / beta) - beta v, with the pending z/w update of the previous iteration
-    hipLaunchKernelGGL(k_vec_v<false>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
-                       w.z, h->xt, h->st, h->partB);
+    hipLaunchKernelGGL((k_vec_v<false, VAR>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v,
+                       w.w, w.z, h->xt, h->st, h->partB, w.var);
     hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn,
                        h->partB + h->Gn, h->Gn);
 }
@@ -515,15 +519,16 @@ gsr_status read_info(gsr_handle* h, gsr_solve_info* info, hipStream_t s,
     return GSR_OK;
 }
 
-// PC-LSQR on A (binary64 or binary32 coefficients): x = p o z.  Synchronizes.
-template <typename VT>
+// PC-LSQR on A (binary64 or binary32 coefficients): x = p o z; VAR: also the variance
+// estimate var_out = p^2 o sum (w_i / rho_i)^2.  Synchronizes.
+template <typename VT, bool VAR = false>
 gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
                      const double* p, const double* b, double* x, const gsr_solve_opts& o,
-                     gsr_solve_info* info, hipStream_t s) {
+                     gsr_solve_info* info, hipStream_t s, double* var_out = nullptr) {
     const Geo& g = h->g;
-    GSR_TRY(ensure_work(w, g.m, g.n));
+    GSR_TRY(ensure_work(w, g.m, g.n, VAR));
     GSR_TRY(capture_graph(
-        h, w, [&](hipStream_t cs) { fwd_iteration<VT>(h, w, vals, attT, p, cs); }));
+        h, w, [&](hipStream_t cs) { fwd_iteration<VT, VAR>(h, w, vals, attT, p, cs); }));
     // beta_1 u_1 = b
     hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
                        w.u, nullptr, h->partA);
@@ -535,21 +540,21 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
         launch_fused<VT, false, true>(h, vals, attT, w.u, h->s, h->partB, s, nullptr);
     else
         launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
-    hipLaunchKernelGGL(k_vec_v<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v, w.w,
-                       w.z, h->xt, h->st, h->partB);
+    hipLaunchKernelGGL((k_vec_v<true, VAR>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v,
+                       w.w, w.z, h->xt, h->st, h->partB, w.var);
     hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
     ProfileOut prof;
     if (o.profile)
         GSR_TRY(run_profiled(
             h, o, s,
             [&](hipStream_t cs, const IterEvents* ev) {
-                fwd_iteration<VT>(h, w, vals, attT, p, cs, ev);
+                fwd_iteration<VT, VAR>(h, w, vals, attT, p, cs, ev);
             },
             &prof.ms1, &prof.ms2, &prof.n));
     else
         GSR_TRY(run_iterations(h, w, o, s));
-    hipLaunchKernelGGL(k_final<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, p, w.z, w.w, w.v, x,
-                       h->st);
+    hipLaunchKernelGGL((k_final<true, VAR>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, p, w.z, w.w,
+                       w.v, x, h->st, w.var, var_out);
     HIP_TRY(hipGetLastError());
     return read_info(h, info, s, prof);
 }
@@ -815,6 +820,7 @@ gsr_status gsr_destroy(gsr_handle* h) {
     if (h->cap) (void)hipStreamSynchronize(h->cap);
     (void)hipDeviceSynchronize();
     free_work(h->fwd64);
+    free_work(h->fwd64v);
     free_work(h->fwd32);
     free_work(h->trans);
     dfree(h->vals32);
@@ -960,6 +966,19 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
         info->n_refine = k;
     }
     return GSR_OK;
+}
+
+gsr_status gsr_lsqr_solve_var(gsr_handle* h, const double* b, double* x, double* var,
+                              const gsr_solve_opts* opts, gsr_solve_info* info, void* stream) {
+    g_last_error.clear();
+    if (!h || !x || !var || (!b && h->g.m > 0)) return fail(GSR_E_INVAL, "null argument");
+    const gsr_solve_opts o = opts ? *opts : default_opts();
+    GSR_TRY(check_opts(o));
+    if (o.precision != GSR_F64)
+        return fail(GSR_E_UNSUPPORTED, "the variance estimate is binary64 only");
+    GSR_TRY(set_device(h));
+    return fwd_solve<double, true>(h, h->fwd64v, h->vals, h->attT64, h->p64, b, x, o, info,
+                                   as_stream(stream), var);
 }
 
 gsr_status gsr_lsqr_solve_adjoint(gsr_handle* h, const double* gvec, double* mu, double* lam,

@@ -48,6 +48,7 @@ struct LsqrState {
     double fb;            // extra z += fb w after an exact beta = 0 breakdown
     double anorm2, bnorm, rnorm, arnorm, znorm2;
     double atol, btol;
+    double rinv, rinv_b;  // 1/rho of the pending update and of a breakdown step (variances)
     int32_t itn, itnlim, fixed, istop, stop, pending, pend_b, nonfinite;
 };
 
@@ -141,19 +142,22 @@ static __global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const do
 //          v~ = p o s - beta sv v~
 // s is reset to 0 and xt = p o v~ (the operand of the next aprod 1) is written.
 // Partials (4 rows of G): sum v~^2, sum z^2, sum z w, sum w^2.
-template <bool INIT>
+// VAR: also the variance estimate var += (w / rho)^2 with the w of the pending update.
+template <bool INIT, bool VAR = false>
 static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __restrict__ s,
                                                   const double* __restrict__ p,
                                                   double* __restrict__ v, double* __restrict__ w,
                                                   double* __restrict__ z, double* __restrict__ xt,
                                                   const LsqrState* __restrict__ st,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials,
+                                                  double* __restrict__ var = nullptr) {
     __shared__ double sh[kBlock / kWave];
     if (!INIT && st->stop) return;
     const bool pending = !INIT && st->pending;
     const double f1 = st->f1, f2 = st->f2, sv = st->sv;
     const double c1 = INIT ? 0.0 : st->beta * st->sv;
     const double su = st->su;  // s holds A^T u~ unnormalized
+    const double rinv = st->rinv;
     double avv = 0.0, azz = 0.0, azw = 0.0, aww = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
@@ -164,10 +168,15 @@ static __global__ __launch_bounds__(kBlock) void k_vec_v(int64_t n, double* __re
             vn = p[j] * (su * sj);
             z[j] = 0.0;
             w[j] = 0.0;
+            if (VAR) var[j] = 0.0;
         } else {
             const double vj = v[j];
             if (pending) {
                 const double wj = w[j];
+                if (VAR) {
+                    const double d = wj * rinv;
+                    var[j] = fma(d, d, var[j]);
+                }
                 const double zj = fma(f1, wj, z[j]);
                 const double wn = sv * vj - f2 * wj;
                 z[j] = zj;
@@ -254,25 +263,37 @@ static __global__ __launch_bounds__(kBlock) void k_vec_zw(int64_t n, const doubl
     if (threadIdx.x == 0) partials[2 * G + blockIdx.x] = tot;
 }
 
-// End of a solve: apply the pending updates, out = p o z (PRE) or z.
-template <bool PRE>
+// End of a solve: apply the pending updates, out = p o z (PRE) or z.  VAR: the same for the
+// variance estimate, var_out = p^2 o var (PRE) or var.
+template <bool PRE, bool VAR = false>
 static __global__ void k_final(int64_t n, const double* __restrict__ p, double* __restrict__ z,
                         double* __restrict__ w, const double* __restrict__ v,
-                        double* __restrict__ out, const LsqrState* __restrict__ st) {
+                        double* __restrict__ out, const LsqrState* __restrict__ st,
+                        double* __restrict__ var = nullptr, double* __restrict__ var_out = nullptr) {
     const bool pending = st->pending, pend_b = st->pend_b;
     const double f1 = st->f1, f2 = st->f2, sv = st->sv, fb = st->fb;
+    const double rinv = st->rinv, rinv_b = st->rinv_b;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         double zj = z[j];
+        double vr = VAR ? var[j] : 0.0;
         if (pending) {
             const double wj = w[j];
             zj = fma(f1, wj, zj);
+            if (VAR) vr = fma(wj * rinv, wj * rinv, vr);
             const double wn = sv * v[j] - f2 * wj;
-            if (pend_b) zj = fma(fb, wn, zj);
+            if (pend_b) {
+                zj = fma(fb, wn, zj);
+                if (VAR) vr = fma(wn * rinv_b, wn * rinv_b, vr);
+            }
             w[j] = wn;
         }
         z[j] = zj;
         out[j] = PRE ? p[j] * zj : zj;
+        if (VAR) {
+            var[j] = vr;
+            var_out[j] = PRE ? p[j] * p[j] * vr : vr;
+        }
     }
 }
 
@@ -354,6 +375,7 @@ __device__ __forceinline__ void scal_beta(LsqrState* st, double ss) {
     const double c = rhobar / rho;
     const double phi = c * st->phibar;
     st->fb = phi / rho;
+    st->rinv_b = 1.0 / rho;
     st->pend_b = 1;
     st->rhobar = -c * alpha;
     st->phibar = 0.0;
@@ -380,6 +402,7 @@ __device__ __forceinline__ void scal_alpha(LsqrState* st, double vv, double zz, 
     st->phibar = s * phibar;
     st->f1 = phi / rho;
     st->f2 = theta / rho;
+    st->rinv = 1.0 / rho;
     st->pending = 1;
     st->alpha = alpha;
     st->sv = alpha > 0.0 ? 1.0 / alpha : 0.0;

@@ -26,7 +26,8 @@ _STATUS = {0: "GSR_OK", -1: "GSR_E_INVAL", -2: "GSR_E_LAYOUT", -3: "GSR_E_NOMEM"
 EXPORTS = (
     "gsr_abi_version", "gsr_status_string", "gsr_last_error", "gsr_lsqr_setup", "gsr_destroy",
     "gsr_get_size", "gsr_aprod1", "gsr_aprod2", "gsr_aprod1_f32v", "gsr_aprod2_f32v",
-    "gsr_precond", "gsr_residual", "gsr_lsqr_solve", "gsr_lsqr_solve_adjoint", "gsr_grad_vals",
+    "gsr_precond", "gsr_residual", "gsr_lsqr_solve", "gsr_lsqr_solve_var",
+    "gsr_lsqr_solve_adjoint", "gsr_grad_vals",
     "gsr_batch_setup", "gsr_batch_destroy", "gsr_batch_col_offsets", "gsr_batch_aprod1",
     "gsr_batch_aprod2", "gsr_batch_solve",
 )
@@ -100,6 +101,8 @@ def load() -> ctypes.CDLL:
         "gsr_residual": (st, [vp, vp, vp, vp, vp]),
         "gsr_lsqr_solve": (st, [vp, vp, vp, ctypes.POINTER(SolveOpts),
                                 ctypes.POINTER(SolveInfo), vp]),
+        "gsr_lsqr_solve_var": (st, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                    ctypes.POINTER(SolveInfo), vp]),
         "gsr_lsqr_solve_adjoint": (st, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                         ctypes.POINTER(SolveInfo), vp]),
         "gsr_grad_vals": (st, [vp, vp, vp, vp, vp, vp, vp]),
@@ -236,6 +239,18 @@ def gsr_lsqr_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=None) 
                                  _dev(x, torch.float64, h.n, "x"),
                                  ctypes.byref(opts) if opts is not None else None,
                                  ctypes.byref(info), _stream(stream)), "gsr_lsqr_solve")
+    return info.as_dict()
+
+
+def gsr_lsqr_solve_var(h: Handle, b, x, var, opts: SolveOpts | None = None,
+                       stream=None) -> dict:
+    """PC-LSQR plus the variance estimate var ~ diag((A^T A)^-1) (binary64)."""
+    info = SolveInfo()
+    _check(load().gsr_lsqr_solve_var(h.ptr, _dev(b, torch.float64, h.m, "b"),
+                                     _dev(x, torch.float64, h.n, "x"),
+                                     _dev(var, torch.float64, h.n, "var"),
+                                     ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(info), _stream(stream)), "gsr_lsqr_solve_var")
     return info.as_dict()
 
 

@@ -282,3 +282,75 @@ def test_full_size_products_and_first_iterations_vs_oracle():
         xo, _ = S.lsqr(b, itnlim=k, fixed=True)
         assert rel(host(xg), xo) <= 1e-10
     h.close()
+
+
+@pytest.mark.parametrize("k", [1, 5, 20, 40, 100])
+def test_variance_estimate_vs_oracle(cfg_small, k):
+    c = cfg_small
+    S, h = c["S"], c["h"]
+    x = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    var = torch.full((S.n,), -1.0, dtype=torch.float64, device="cuda")
+    o = gsr.solve_opts(itnlim=k, fixed_iters=True)
+    info = gsr.gsr_lsqr_solve_var(h, cuda(c["b"]), x, var, o)
+    xo, vo, io = S.lsqr_var(c["b"], itnlim=k, fixed=True)
+    assert info["itn"] == io["itn"] == k
+    assert rel(host(x), xo) <= 1e-10
+    # a sum of k positive terms (w_i / rho_i)^2 per column.  Up to convergence (~45 steps on
+    # this system) each term is fixed to rounding; after it the Lanczos vectors lose
+    # orthogonality and the new terms are shaped by rounding: the oracle itself moves by
+    # ~1e-4 (relative, per entry) at 100 steps when b is perturbed by one ulp, so the bound
+    # there only says both sides accumulate the same estimate
+    v = host(var)
+    assert (v >= 0).all()
+    tol = 1e-10 if k <= 40 else 1e-2
+    np.testing.assert_allclose(v, vo, rtol=tol, atol=0)
+    if k == 100:
+        v40 = torch.empty_like(var)
+        gsr.gsr_lsqr_solve_var(h, cuda(c["b"]), x, v40, gsr.solve_opts(itnlim=40))
+        assert (v >= host(v40)).all()  # the estimate only grows with the steps
+    # the solution is that of the plain solve, whose kernels share this arithmetic
+    x2 = torch.empty_like(x)
+    info2 = gsr.gsr_lsqr_solve(h, cuda(c["b"]), x2, o)
+    assert rel(host(x), host(x2)) <= 1e-14
+    assert info2["itn"] == info["itn"]
+
+
+def test_variance_estimate_converged_empty_columns_and_zero_rhs(cfg_small):
+    c = cfg_small
+    S, h = c["S"], c["h"]
+    x = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    var = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    # stopped by the tolerances: the same number of steps as the oracle (+-1, the stopping
+    # tests compare rounded estimates), and the estimate of that many steps
+    o = gsr.solve_opts(itnlim=500, fixed_iters=False, atol=1e-13, btol=1e-13)
+    info = gsr.gsr_lsqr_solve_var(h, cuda(c["b"]), x, var, o)
+    _, io = S.lsqr(c["b"], itnlim=500, fixed=False, atol=1e-13, btol=1e-13)
+    assert info["istop"] in (1, 2) and abs(info["itn"] - io["itn"]) <= 1
+    xo, vo, _ = S.lsqr_var(c["b"], itnlim=info["itn"], fixed=True)
+    assert rel(host(x), xo) <= 1e-10
+    np.testing.assert_allclose(host(var), vo, rtol=1e-8, atol=0)
+    # binary32-stored coefficients have no variance form
+    with pytest.raises(gsr.GsrError):
+        gsr.gsr_lsqr_solve_var(h, cuda(c["b"]), x, var,
+                               gsr.solve_opts(itnlim=3, precision=gsr.GSR_F32V))
+    # columns no observation touches: p = 0 and a zero estimate on both sides
+    sh2 = synth.Shape(5, 12, 12, 8, 200, seed=8)
+    sysd2 = synth.system(sh2)
+    S2 = oracle_system(sysd2)
+    h2, _ = open_system(sysd2, allow_empty_cols=True)
+    b2 = S2.aprod1(synth.x_true(sh2)) + synth.noise(sh2)
+    x2 = torch.empty(S2.n, dtype=torch.float64, device="cuda")
+    var2 = torch.full((S2.n,), -1.0, dtype=torch.float64, device="cuda")
+    for k in (1, 3, 10):
+        gsr.gsr_lsqr_solve_var(h2, cuda(b2), x2, var2, gsr.solve_opts(itnlim=k))
+        _, vo2, _ = S2.lsqr_var(b2, itnlim=k, fixed=True)
+        v2 = host(var2)
+        assert (vo2 == 0).sum() > 0 and np.array_equal(v2 == 0, vo2 == 0), k
+        np.testing.assert_allclose(v2, vo2, rtol=1e-10, atol=0)
+    # zero right-hand side: no step is taken and the estimate is zero
+    var2.fill_(-1.0)
+    info = gsr.gsr_lsqr_solve_var(h2, torch.zeros(S2.m, dtype=torch.float64, device="cuda"),
+                                  x2, var2)
+    assert info["istop"] == 4 and float(x2.abs().max()) == 0.0
+    assert float(var2.abs().max()) == 0.0
+    h2.close()
