@@ -45,7 +45,7 @@ class Info(ctypes.Structure):
     _fields_ = [("itn", ctypes.c_int32), ("istop", ctypes.c_int32),
                 ("rnorm", ctypes.c_double), ("arnorm", ctypes.c_double),
                 ("anorm", ctypes.c_double), ("znorm", ctypes.c_double),
-                ("bnorm", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("acond", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,14 +71,14 @@ def _load():
         lib.or_colnorm.restype = None
         lib.or_colnorm.argtypes = [pd, vp, vp, vp, vp, vp]
         lib.or_pclsqr.restype = ctypes.c_int
-        lib.or_pclsqr.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, vp,
+        lib.or_pclsqr.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, f64, vp,
                                   ctypes.POINTER(Info), vp]
         lib.or_pclsqr_var.restype = ctypes.c_int
-        lib.or_pclsqr_var.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, vp, vp,
-                                      ctypes.POINTER(Info)]
+        lib.or_pclsqr_var.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, f64, vp,
+                                      vp, ctypes.POINTER(Info)]
         lib.or_lsqr_transposed.restype = ctypes.c_int
-        lib.or_lsqr_transposed.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, vp,
-                                           ctypes.POINTER(Info)]
+        lib.or_lsqr_transposed.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, f64,
+                                           vp, ctypes.POINTER(Info)]
         lib.or_residual.restype = None
         lib.or_residual.argtypes = [pd, vp, vp, vp, vp, vp, vp, vp]
         lib.or_refine.restype = i32
@@ -164,7 +164,7 @@ class System:
         return p
 
     def lsqr(self, b, itnlim=100, fixed=True, atol=1e-14, btol=1e-14, precond=True, p=None,
-             hist=False):
+             hist=False, conlim=0.0):
         """PC-LSQR.  Returns (x, info dict[, per-iteration rnorm estimates])."""
         b = _f64(b)
         assert b.size == self.m
@@ -174,13 +174,13 @@ class System:
         info = Info()
         h = np.zeros(max(itnlim, 1)) if hist else None
         _load().or_pclsqr(*self._args(), _p(p) if precond else None, _p(b), int(itnlim),
-                          int(bool(fixed)), float(atol), float(btol), _p(x), ctypes.byref(info),
-                          _p(h))
+                          int(bool(fixed)), float(atol), float(btol), float(conlim), _p(x),
+                          ctypes.byref(info), _p(h))
         if hist:
             return x, info.as_dict(), h[: info.itn]
         return x, info.as_dict()
 
-    def lsqr_var(self, b, itnlim=100, fixed=True, atol=1e-14, btol=1e-14, p=None):
+    def lsqr_var(self, b, itnlim=100, fixed=True, atol=1e-14, btol=1e-14, p=None, conlim=0.0):
         """PC-LSQR with the variance estimate: returns (x, var, info dict); var estimates
         diag((A^T A)^-1)."""
         b = _f64(b)
@@ -190,11 +190,12 @@ class System:
         x, var = np.empty(self.n), np.empty(self.n)
         info = Info()
         _load().or_pclsqr_var(*self._args(), _p(_f64(p)), _p(b), int(itnlim), int(bool(fixed)),
-                              float(atol), float(btol), _p(x), _p(var), ctypes.byref(info))
+                              float(atol), float(btol), float(conlim), _p(x), _p(var),
+                              ctypes.byref(info))
         return x, var, info.as_dict()
 
     def lsqr_transposed(self, g, itnlim=1000, fixed=False, atol=1e-14, btol=1e-14, p=None,
-                        precond=True):
+                        precond=True, conlim=0.0):
         """Minimum-norm mu with A^T mu = g (LSQR on D A^T)."""
         g = _f64(g)
         assert g.size == self.n
@@ -204,7 +205,7 @@ class System:
         info = Info()
         _load().or_lsqr_transposed(*self._args(), _p(p) if precond else None, _p(g),
                                    int(itnlim), int(bool(fixed)), float(atol), float(btol),
-                                   _p(mu), ctypes.byref(info))
+                                   float(conlim), _p(mu), ctypes.byref(info))
         return mu, info.as_dict()
 
     def residual(self, b, x) -> np.ndarray:

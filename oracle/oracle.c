@@ -26,7 +26,8 @@
  *     the global column is 5*n_stars + 3*n_dfa + n_instr;
  *   - "norm of the column" is the Euclidean norm and p holds its reciprocal;
  *     an all-zero column gets p = 0;
- *   - the stopping rule is Paige & Saunders' pair of tests with atol/btol, or a
+ *   - the stopping rule is Paige & Saunders' tests (atol/btol, the condition
+ *     estimate against conlim, and the same three at machine precision), or a
  *     fixed iteration count; an exact breakdown (alpha or beta = 0) always stops;
  *   - the variances the paper updates every iteration (Section 3, flowchart
  *     paragraph) are Paige & Saunders' estimate of diag((A^T A)^-1): the sum over
@@ -49,12 +50,15 @@ typedef struct {
 typedef struct {
     int32_t itn;     /* iterations performed                                  */
     int32_t istop;   /* 0 limit, 1 test1 (compatible), 2 test2 (LS), 3 exact
-                        breakdown, 4 zero right-hand side                      */
+                        breakdown, 4 zero right-hand side, 5 acond > conlim,
+                        6/7/8 test1/test2/1/acond at machine precision         */
     double rnorm;    /* ||b - B z|| estimate  (phibar)                        */
     double arnorm;   /* ||B^T (b - B z)|| estimate (phibar * alpha * |c|)     */
     double anorm;    /* Frobenius estimate of ||B||                           */
     double znorm;    /* ||z|| (exact)                                         */
     double bnorm;    /* ||b||                                                 */
+    double acond;    /* estimate of cond(B) = ||B||_F ||B^+||_F: anorm times
+                        sqrt(sum ||w_i / rho_i||^2)                           */
 } or_info;
 
 /* Number of unknowns: astrometric, attitude, instrumental and global sections. */
@@ -205,10 +209,15 @@ static void scal(double *v, int64_t n, double a)
  * test2 ||B^T r|| <= atol ||B|| ||r||, with ||r|| = phibar_{i+1},
  * ||B^T r|| = phibar_{i+1} alpha_{i+1} |c_i| and ||B||^2 estimated by
  * sum (alpha_i^2 + beta_{i+1}^2).  alpha or beta exactly zero ends the iteration.
+ * Then, in this order: test3 = 1 / acond <= 1 / conlim (conlim > 0), and, at machine
+ * precision (1 + t <= 1), t1 = test1 / (1 + ||B|| ||z|| / ||b||), test2 = ||B^T r|| /
+ * (||B|| ||r||), test3; acond = ||B|| (sum_i ||w_i / rho_i||^2)^(1/2) (Paige & Saunders,
+ * Section 5.1).
  * If `hist_rnorm` is not NULL it receives phibar_{i+1} for i = 1..itn.
  */
 static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t fixed, double atol,
-                     double btol, double *z, or_info *info, double *hist_rnorm, double *var)
+                     double btol, double conlim, double *z, or_info *info, double *hist_rnorm,
+                     double *var)
 {
     const int64_t m = op_rows(op), n = op_cols(op);
     double *u = malloc((size_t)m * sizeof(double));
@@ -232,7 +241,8 @@ static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t f
         scal(v, n, 1.0 / alpha);
     memcpy(w, v, (size_t)n * sizeof(double));
 
-    double rhobar = alpha, phibar = beta, anorm2 = 0.0;
+    double rhobar = alpha, phibar = beta, anorm2 = 0.0, ddnorm = 0.0;
+    const double ctol = conlim > 0.0 ? 1.0 / conlim : 0.0;
     info->rnorm = beta;
     info->arnorm = alpha * beta;
     if (beta == 0.0) {
@@ -268,10 +278,11 @@ static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t f
         phibar = s * phibar;
         const double t1 = phi / rho, t2 = theta / rho;
         for (int64_t j = 0; j < n; ++j) {
-            if (var) { /* d = w / rho, var += d^2 (w before its update) */
-                const double d = w[j] / rho;
-                var[j] += d * d;
-            }
+            /* d = w / rho (w before its update): var += d^2, ddnorm += ||d||^2 */
+            const double dj = w[j] / rho;
+            if (var)
+                var[j] += dj * dj;
+            ddnorm += dj * dj;
             z[j] += t1 * w[j];
             w[j] = v[j] - t2 * w[j];
         }
@@ -281,6 +292,7 @@ static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t f
         info->arnorm = phibar * alpha * fabs(c);
         info->anorm = sqrt(anorm2);
         info->znorm = nrm2(z, n);
+        info->acond = info->anorm * sqrt(ddnorm);
         if (hist_rnorm)
             hist_rnorm[itn - 1] = phibar;
 
@@ -295,6 +307,28 @@ static int lsqr_core(const or_op *op, const double *b, int32_t itnlim, int32_t f
             }
             if (info->arnorm <= atol * info->anorm * info->rnorm) {
                 info->istop = 2;
+                break;
+            }
+            /* the remaining tests of Paige & Saunders (Section 6): the condition estimate
+             * against conlim, then the three tests with the tolerances at machine precision */
+            const double test2 = info->arnorm / (info->anorm * info->rnorm);
+            const double test3 = 1.0 / info->acond;
+            const double t1 = (info->rnorm / info->bnorm) /
+                              (1.0 + info->anorm * info->znorm / info->bnorm);
+            if (test3 <= ctol) {
+                info->istop = 5;
+                break;
+            }
+            if (1.0 + t1 <= 1.0) {
+                info->istop = 6;
+                break;
+            }
+            if (1.0 + test2 <= 1.0) {
+                info->istop = 7;
+                break;
+            }
+            if (1.0 + test3 <= 1.0) {
+                info->istop = 8;
                 break;
             }
         }
@@ -314,12 +348,13 @@ done:
  */
 int or_pclsqr(const or_dims *d, const double *vals, const int32_t *star, const int32_t *att,
               const int32_t *instr, const double *p, const double *b, int32_t itnlim,
-              int32_t fixed, double atol, double btol, double *x, or_info *info,
-              double *hist_rnorm)
+              int32_t fixed, double atol, double btol, double conlim, double *x,
+              or_info *info, double *hist_rnorm)
 {
     const int64_t n = or_n_cols(d);
     or_op op = {d, vals, star, att, instr, p, 0, malloc((size_t)n * sizeof(double))};
-    const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, x, info, hist_rnorm, NULL);
+    const int rc =
+        lsqr_core(&op, b, itnlim, fixed, atol, btol, conlim, x, info, hist_rnorm, NULL);
     if (p)
         for (int64_t j = 0; j < n; ++j)
             x[j] *= p[j];
@@ -334,12 +369,12 @@ int or_pclsqr(const or_dims *d, const double *vals, const int32_t *star, const i
  */
 int or_pclsqr_var(const or_dims *d, const double *vals, const int32_t *star,
                   const int32_t *att, const int32_t *instr, const double *p, const double *b,
-                  int32_t itnlim, int32_t fixed, double atol, double btol, double *x,
-                  double *var, or_info *info)
+                  int32_t itnlim, int32_t fixed, double atol, double btol, double conlim,
+                  double *x, double *var, or_info *info)
 {
     const int64_t n = or_n_cols(d);
     or_op op = {d, vals, star, att, instr, p, 0, malloc((size_t)n * sizeof(double))};
-    const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, x, info, NULL, var);
+    const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, conlim, x, info, NULL, var);
     if (p)
         for (int64_t j = 0; j < n; ++j) {
             x[j] *= p[j];
@@ -356,15 +391,15 @@ int or_pclsqr_var(const or_dims *d, const double *vals, const int32_t *star,
  */
 int or_lsqr_transposed(const or_dims *d, const double *vals, const int32_t *star,
                        const int32_t *att, const int32_t *instr, const double *p, const double *g,
-                       int32_t itnlim, int32_t fixed, double atol, double btol, double *mu,
-                       or_info *info)
+                       int32_t itnlim, int32_t fixed, double atol, double btol, double conlim,
+                       double *mu, or_info *info)
 {
     const int64_t n = or_n_cols(d);
     double *rhs = malloc((size_t)n * sizeof(double));
     for (int64_t j = 0; j < n; ++j)
         rhs[j] = p ? p[j] * g[j] : g[j];
     or_op op = {d, vals, star, att, instr, p, 1, malloc((size_t)n * sizeof(double))};
-    const int rc = lsqr_core(&op, rhs, itnlim, fixed, atol, btol, mu, info, NULL, NULL);
+    const int rc = lsqr_core(&op, rhs, itnlim, fixed, atol, btol, conlim, mu, info, NULL, NULL);
     free(op.tmp);
     free(rhs);
     return rc;
@@ -407,7 +442,7 @@ int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
     while (k < max_outer) {
         or_info info;
         or_pclsqr(d, vals_lo, star, att, instr, p_lo, r, inner_itnlim, inner_fixed, inner_atol,
-                  inner_btol, dx, &info, NULL);
+                  inner_btol, 0.0, dx, &info, NULL);
         if (inner_itn)
             inner_itn[k] = info.itn;
         for (int64_t j = 0; j < n; ++j)

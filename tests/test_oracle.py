@@ -174,6 +174,55 @@ def test_variance_estimate_exact_after_n_steps():
     assert np.all(var10 <= ref * (1 + 1e-9)) and np.max(np.abs(var10 - ref) / ref) > 0.1
 
 
+# scipy numbers the stopping reasons 1 compatible, 2 least squares, 3 conlim, 4/5/6 the same
+# three at machine precision; the oracle keeps 3/4 for an exact breakdown and a zero b
+_SCIPY_ISTOP = {1: 1, 2: 2, 3: 5, 4: 6, 5: 7, 6: 8}
+
+
+@pytest.mark.parametrize("shape", [synth.Shape(40, 10, 60, 30, 40, seed=23),
+                                   synth.Shape(4, 25, 40, 6, 10, seed=10)])
+@pytest.mark.parametrize("noise", [True, False])
+@pytest.mark.parametrize("atol,btol,conlim", [(0.0, 0.0, 0.0), (1e-8, 1e-8, 0.0),
+                                              (0.0, 0.0, 30.0), (1e-14, 1e-14, 0.0)])
+def test_stopping_rules_match_scipy_lsqr(shape, noise, atol, btol, conlim):
+    """Every Paige & Saunders stopping test (tolerances, condition limit, machine precision):
+    the same step and the same reason as scipy's LSQR on A diag(p), and the same condition
+    estimate."""
+    s, S = _system(shape)
+    A = csr(s["dims"], s["vals"], s["star"], s["att"], s["instr"])
+    b = A @ synth.x_true(shape) + (synth.noise(shape) if noise else 0.0)
+    p = S.colnorm()
+    Ab = spla.LinearOperator(A.shape, matvec=lambda z: A @ (p * z),
+                             rmatvec=lambda y: p * (A.T @ y), dtype=np.float64)
+    x, info = S.lsqr(b, itnlim=2000, fixed=False, atol=atol, btol=btol, conlim=conlim)
+    res = spla.lsqr(Ab, b, atol=atol, btol=btol, conlim=conlim if conlim > 0 else 1e300,
+                    iter_lim=2000)
+    assert info["itn"] == res[2]
+    assert info["istop"] == _SCIPY_ISTOP[res[1]]
+    assert abs(info["acond"] - res[6]) <= 1e-3 * res[6]
+    assert np.linalg.norm(x - p * res[0]) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_condition_estimate_after_n_steps():
+    """acond = ||B|| (sum ||w_i / rho_i||^2)^(1/2) is ||B||_F ||B^+||_F once the Krylov space is
+    complete (B = A D, 29 unknowns), and grows towards it."""
+    shape = synth.Shape(2, 30, 30, 4, 6, seed=93)
+    s, S = _system(shape)
+    A = dense(s["dims"], s["vals"], s["star"], s["att"], s["instr"])
+    p = S.colnorm()
+    B = A * p
+    sv = np.linalg.svd(B, compute_uv=False)
+    ref = np.sqrt((sv ** 2).sum()) * np.sqrt((sv ** -2.0).sum())
+    b = A @ synth.x_true(shape) + synth.noise(shape)
+    _, info = S.lsqr(b, itnlim=S.n, fixed=True)
+    assert abs(info["acond"] - ref) <= 1e-3 * ref
+    _, info10 = S.lsqr(b, itnlim=10, fixed=True)
+    assert info10["acond"] < 0.9 * ref
+    # a condition limit below the estimate stops at the first step that exceeds it
+    _, ic = S.lsqr(b, itnlim=S.n, fixed=False, atol=0.0, btol=0.0, conlim=info10["acond"])
+    assert ic["istop"] == 5 and ic["itn"] <= 10 and ic["acond"] >= info10["acond"] * (1 - 1e-12)
+
+
 def test_lsqr_converged_vs_lstsq_and_precond_invariance():
     shape = synth.Shape(4, 25, 40, 6, 10, seed=10)
     s, S = _system(shape)
