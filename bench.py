@@ -334,6 +334,27 @@ def form_batch(args) -> dict:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     err = float(torch.linalg.norm(Xs - Xd) / torch.linalg.norm(Xd))
+    # the same batch solved to a tolerance: every pair stops on its own tests, systems whose
+    # pairs have all stopped drop out of the passes
+    tol = 1e-10
+    copts = gsr.solve_opts(itnlim=2000, fixed_iters=False, atol=tol, btol=tol)
+    gsr.gsr_batch_solve(bt, Bd, Xs, copts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = gsr.gsr_batch_solve(bt, Bd, Xs, copts)
+    torch.cuda.synchronize()
+    dtc = (time.perf_counter() - t0) / args.steps
+    itns = np.array([f["itn"] for f in infos])
+    stops = np.array([f["istop"] for f in infos])
+    converged = {
+        "atol": tol, "btol": tol, "latency_ms_per_solve": round(1e3 * dtc, 3),
+        "systems_per_s": round(len(shapes) / dtc, 3),
+        "itn_min": int(itns.min()), "itn_median": float(np.median(itns)),
+        "itn_max": int(itns.max()),
+        "istop_counts": {str(int(v)): int((stops == v).sum()) for v in np.unique(stops)},
+        "solution_rel_err_vs_x_true": float(torch.linalg.norm(Xs - Xd) / torch.linalg.norm(Xd)),
+    }
     bt.close()
     return {
         "metric": "batched PC-LSQR: systems/s and per-system latency",
@@ -347,6 +368,7 @@ def form_batch(args) -> dict:
         "latency_ms_per_solve": round(1e3 * dt, 3),
         "pairs_per_s": round(len(shapes) * k / dt, 2),
         "solution_rel_err_vs_x_true": err,
+        "converged": converged,
     }
 
 

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 1
+#define GSR_ABI_VERSION 2
 
 typedef enum gsr_status {
     GSR_OK = 0,
@@ -90,12 +90,18 @@ typedef struct gsr_solve_opts {
     int32_t check_every; /* iterations between host reads of the stop flag (0 = 16)       */
     int32_t profile;     /* 1: launch the iterations one by one (no graph) with HIP events
                             around every product; averages go to gsr_solve_info           */
+    double conlim;       /* used when fixed_iters = 0: stop once the condition estimate
+                            acond of A D reaches conlim (0 = no limit).  After the atol /
+                            btol and conlim tests, Paige & Saunders' three tests at
+                            machine precision also stop the iteration (istop 6, 7, 8)    */
 } gsr_solve_opts;
 
 typedef struct gsr_solve_info {
     int32_t itn;      /* LSQR iterations performed (summed over refinement steps)          */
     int32_t istop;    /* 0 itnlim reached, 1 compatible-system test, 2 least-squares test,
-                         3 exact breakdown, 4 zero right-hand side                         */
+                         3 exact breakdown, 4 zero right-hand side, 5 acond >= conlim,
+                         6 / 7 / 8 the compatible, least-squares and condition tests with
+                         the tolerances at machine precision (1 + t <= 1)                 */
     int32_t n_refine; /* outer steps taken (GSR_F32V), 1 otherwise                         */
     int32_t reserved;
     double rnorm;     /* estimate of ||b - A x|| (last inner solve)                        */
@@ -110,6 +116,9 @@ typedef struct gsr_solve_info {
                          (block-sum reduction and attitude pass; all of aprod 2 if unfused) */
     int32_t n_pass;   /* number of iterations averaged                                      */
     int32_t fused;    /* 1 if the row-ordered pass was fused                                */
+    double acond;     /* estimate of cond(A D) = ||A D||_F ||(A D)^+||_F: anorm times
+                         (sum_i ||w_i / rho_i||^2)^(1/2) (Paige & Saunders, Section 5.1);
+                         after an exact breakdown it omits the last step's term           */
 } gsr_solve_info;
 
 typedef struct gsr_handle gsr_handle;

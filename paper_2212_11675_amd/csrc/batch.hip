@@ -767,7 +767,7 @@ static __global__ __launch_bounds__(256) void k_bscal(LsqrState* __restrict__ st
                                                       const SysDesc* __restrict__ sys, int n_sys,
                                                       const double* __restrict__ part, int nseg,
                                                       int32_t itnlim, int32_t fixed, double atol,
-                                                      double btol, int32_t k_used) {
+                                                      double btol, double conlim, int32_t k_used) {
     const int pair = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (pair >= n_sys * K) return;
     const int sidx = pair / K, j = pair % K;
@@ -780,7 +780,7 @@ static __global__ __launch_bounds__(256) void k_bscal(LsqrState* __restrict__ st
     if (STEP == BS_INIT1) {
         const double ss = pair_sum<K>(part, 0, nseg, first, count, j);
         if (threadIdx.x % kWave == 0) {
-            scal_init1(ps, ss, itnlim, fixed, atol, btol);
+            scal_init1(ps, ss, itnlim, fixed, atol, btol, conlim);
             if (j >= k_used) {  // padding right-hand side: never iterates
                 ps->stop = 1;
                 ps->istop = 4;
@@ -1015,19 +1015,19 @@ void bscal(gsr_batch* b, int step, int nseg, const gsr_solve_opts& o, hipStream_
         case BS_INIT1:
             hipLaunchKernelGGL((k_bscal<BS_INIT1, K>), grid, block, 0, s, b->st, b->d_sys,
                                b->n_sys, b->part, nseg, o.itnlim, o.fixed_iters, o.atol, o.btol,
-                               b->k);
+                               o.conlim, b->k);
             break;
         case BS_INIT2:
             hipLaunchKernelGGL((k_bscal<BS_INIT2, K>), grid, block, 0, s, b->st, b->d_sys,
-                               b->n_sys, b->part, nseg, 0, 0, 0.0, 0.0, b->k);
+                               b->n_sys, b->part, nseg, 0, 0, 0.0, 0.0, 0.0, b->k);
             break;
         case BS_BETA:
             hipLaunchKernelGGL((k_bscal<BS_BETA, K>), grid, block, 0, s, b->st, b->d_sys,
-                               b->n_sys, b->part, nseg, 0, 0, 0.0, 0.0, b->k);
+                               b->n_sys, b->part, nseg, 0, 0, 0.0, 0.0, 0.0, b->k);
             break;
         default:
             hipLaunchKernelGGL((k_bscal<BS_ALPHA, K>), grid, block, 0, s, b->st, b->d_sys,
-                               b->n_sys, b->part, nseg, 0, 0, 0.0, 0.0, b->k);
+                               b->n_sys, b->part, nseg, 0, 0, 0.0, 0.0, 0.0, b->k);
     }
 }
 
@@ -1380,6 +1380,8 @@ gsr_status gsr_batch_solve(gsr_batch* b, const double* B, double* X, const gsr_s
     o.atol = o.btol = 1e-14;
     if (opts) o = *opts;
     if (o.itnlim < 0) return fail(GSR_E_INVAL, "itnlim < 0");
+    if (!(o.atol >= 0) || !(o.btol >= 0) || !(o.conlim >= 0))
+        return fail(GSR_E_INVAL, "atol, btol and conlim must be >= 0");
     if (o.precision != GSR_F64) return fail(GSR_E_UNSUPPORTED, "batched solve is binary64 only");
     HIP_TRY(hipSetDevice(b->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1457,6 +1459,7 @@ gsr_status gsr_batch_solve(gsr_batch* b, const double* B, double* X, const gsr_s
             f.anorm = std::sqrt(t.anorm2);
             f.znorm = std::sqrt(t.znorm2);
             f.bnorm = t.bnorm;
+            f.acond = std::sqrt(t.anorm2) * std::sqrt(t.ddnorm);
         }
     }
     if (nonfinite) return fail(GSR_E_BREAKDOWN, "non-finite value in a batched recurrence");

@@ -514,6 +514,7 @@ gsr_status read_info(gsr_handle* h, gsr_solve_info* info, hipStream_t s,
         info->anorm = std::sqrt(t.anorm2);
         info->znorm = std::sqrt(t.znorm2);
         info->bnorm = t.bnorm;
+        info->acond = std::sqrt(t.anorm2) * std::sqrt(t.ddnorm);
     }
     if (t.nonfinite) return fail(GSR_E_BREAKDOWN, "non-finite value in the LSQR recurrence");
     return GSR_OK;
@@ -533,7 +534,7 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
     hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
                        w.u, nullptr, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gm,
-                       o.itnlim, o.fixed_iters, o.atol, o.btol);
+                       o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim);
     // alpha_1 v_1 = p o A^T u_1  (the initial aprod 2)
     fill(h->s, g.n, 0.0, s);
     if (h->fused)
@@ -569,7 +570,7 @@ gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_
     hipLaunchKernelGGL(k_copy_norm<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, gvec, h->p64,
                        w.u, h->xt, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn,
-                       o.itnlim, o.fixed_iters, o.atol, o.btol);
+                       o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim);
     fill(w.w, g.m, 0.0, s);
     fill(w.z, g.m, 0.0, s);
     // alpha_1 v_1 = A D u_1 (and, fused, s = A^T v~_1 for the first u-step)
@@ -611,6 +612,7 @@ gsr_solve_opts default_opts() {
 gsr_status check_opts(const gsr_solve_opts& o) {
     if (o.itnlim < 0) return fail(GSR_E_INVAL, "itnlim < 0");
     if (!(o.atol >= 0) || !(o.btol >= 0)) return fail(GSR_E_INVAL, "atol/btol must be >= 0");
+    if (!(o.conlim >= 0)) return fail(GSR_E_INVAL, "conlim must be >= 0");
     if (o.precision != GSR_F64 && o.precision != GSR_F32V)
         return fail(GSR_E_INVAL, "unknown precision %d", o.precision);
     if (o.precision == GSR_F32V && o.max_refine < 1) return fail(GSR_E_INVAL, "max_refine < 1");

@@ -49,6 +49,8 @@ struct LsqrState {
     double anorm2, bnorm, rnorm, arnorm, znorm2;
     double atol, btol;
     double rinv, rinv_b;  // 1/rho of the pending update and of a breakdown step (variances)
+    double ddnorm;        // sum ||w_i / rho_i||^2 (condition estimate)
+    double ctol;          // 1 / conlim (0: no condition test)
     int32_t itn, itnlim, fixed, istop, stop, pending, pend_b, nonfinite;
 };
 
@@ -311,13 +313,14 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
 
 // beta_1 = ||b||, u = b / beta_1.
 __device__ __forceinline__ void scal_init1(LsqrState* st, double ss, int32_t itnlim, int32_t fixed,
-                                           double atol, double btol) {
+                                           double atol, double btol, double conlim) {
     const double beta = sqrt(ss);
     LsqrState s = {};
     s.itnlim = itnlim;
     s.fixed = fixed;
     s.atol = atol;
     s.btol = btol;
+    s.ctol = conlim > 0.0 ? 1.0 / conlim : 0.0;
     s.beta = beta;
     s.bnorm = beta;
     s.phibar = beta;
@@ -416,28 +419,49 @@ __device__ __forceinline__ void scal_alpha(LsqrState* st, double vv, double zz, 
         st->stop = 1;
         return;
     }
+    // d_i = w_i / rho_i: its squared norm adds to the condition estimate
+    st->ddnorm += ww * st->rinv * st->rinv;
     const double anorm = sqrt(st->anorm2);
     const double znorm = sqrt(st->znorm2);
     if (!(alpha > 0.0)) {
         st->istop = 3;
         st->stop = 1;
-    } else if (!st->fixed &&
-               st->rnorm <= st->btol * st->bnorm + st->atol * anorm * znorm) {
-        st->istop = 1;
-        st->stop = 1;
-    } else if (!st->fixed && st->arnorm <= st->atol * anorm * st->rnorm) {
-        st->istop = 2;
-        st->stop = 1;
+    } else if (!st->fixed) {
+        // Paige & Saunders' tests in their order of precedence: the tolerances, the
+        // condition estimate against conlim, the three at machine precision
+        const double rnorm = st->rnorm, bnorm = st->bnorm;
+        const double acond = anorm * sqrt(st->ddnorm);
+        const double test2 = st->arnorm / (anorm * rnorm);
+        const double test3 = 1.0 / acond;
+        const double t1 = (rnorm / bnorm) / (1.0 + anorm * znorm / bnorm);
+        int32_t why = 0;
+        if (rnorm <= st->btol * bnorm + st->atol * anorm * znorm)
+            why = 1;
+        else if (st->arnorm <= st->atol * anorm * rnorm)
+            why = 2;
+        else if (test3 <= st->ctol)
+            why = 5;
+        else if (1.0 + t1 <= 1.0)
+            why = 6;
+        else if (1.0 + test2 <= 1.0)
+            why = 7;
+        else if (1.0 + test3 <= 1.0)
+            why = 8;
+        if (why) {
+            st->istop = why;
+            st->stop = 1;
+        }
     }
     if (st->itn >= st->itnlim) st->stop = 1;
 }
 
 static __global__ __launch_bounds__(kBlock) void k_scal_init1(LsqrState* st, const double* part,
                                                               int G, int32_t itnlim, int32_t fixed,
-                                                              double atol, double btol) {
+                                                              double atol, double btol,
+                                                              double conlim) {
     __shared__ double sh[kBlock / kWave];
     const double ss = reduce_partials(part, G, sh);
-    if (threadIdx.x == 0) scal_init1(st, ss, itnlim, fixed, atol, btol);
+    if (threadIdx.x == 0) scal_init1(st, ss, itnlim, fixed, atol, btol, conlim);
 }
 
 static __global__ __launch_bounds__(kBlock) void k_scal_init2(LsqrState* st, const double* part,

@@ -14,6 +14,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsr.so")
+ABI_VERSION = 2  # GSR_ABI_VERSION of include/gsr.h
 
 GSR_F64 = 0
 GSR_F32V = 1
@@ -55,7 +56,7 @@ class SolveOpts(ctypes.Structure):
                 ("atol", ctypes.c_double), ("btol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("conlim", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -65,7 +66,7 @@ class SolveInfo(ctypes.Structure):
                 ("anorm", ctypes.c_double), ("znorm", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("ms_pass1", ctypes.c_double),
                 ("ms_pass2", ctypes.c_double), ("n_pass", ctypes.c_int32),
-                ("fused", ctypes.c_int32)]
+                ("fused", ctypes.c_int32), ("acond", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -119,6 +120,9 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
+    if lib.gsr_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {lib.gsr_abi_version()}, this binding "
+                          f"expects {ABI_VERSION}: rebuild it")
     _lib = lib
     return lib
 
@@ -152,10 +156,11 @@ def make_dims(n_rows, n_stars, n_dfa, n_instr, n_glob=1) -> Dims:
 
 
 def solve_opts(itnlim=100, fixed_iters=True, atol=1e-14, btol=1e-14, precision=GSR_F64,
-               max_refine=4, refine_tol=1e-10, check_every=16, profile=False) -> SolveOpts:
+               max_refine=4, refine_tol=1e-10, check_every=16, profile=False,
+               conlim=0.0) -> SolveOpts:
     return SolveOpts(int(itnlim), int(bool(fixed_iters)), float(atol), float(btol),
                      int(precision), int(max_refine), float(refine_tol), int(check_every),
-                     int(bool(profile)))
+                     int(bool(profile)), float(conlim))
 
 
 class Handle:

@@ -134,6 +134,36 @@ def test_batched_converged_solve():
     b.close()
 
 
+def test_batched_condition_limit_stops_every_pair():
+    """conlim: each (system, right-hand side) pair stops on its own condition estimate at the
+    step the oracle's solo solve does."""
+    k = 2
+    b, systems, _ = make_batch(SHAPES[1:], k)
+    B = np.zeros((b.m, k))
+    for s, sysd in enumerate(systems):
+        S = oracle_system(sysd)
+        r0, r1 = b.row_offset[s], b.row_offset[s + 1]
+        for j in range(k):
+            B[r0:r1, j] = S.aprod1(synth.rhs_x(SHAPES[1 + s], j)) + synth.rhs_noise(
+                SHAPES[1 + s], j, S.m)
+    Xd = torch.empty(b.n * k, dtype=torch.float64, device="cuda")
+    o = gsr.solve_opts(itnlim=500, fixed_iters=False, atol=0.0, btol=0.0, conlim=25.0)
+    infos = gsr.gsr_batch_solve(b, cuda(B.ravel()), Xd, o)
+    Xg = host(Xd).reshape(b.n, k)
+    for s, sysd in enumerate(systems):
+        S = oracle_system(sysd)
+        r0, r1 = b.row_offset[s], b.row_offset[s + 1]
+        c0, c1 = b.col_offset[s], b.col_offset[s + 1]
+        for j in range(k):
+            xo, io = S.lsqr(B[r0:r1, j], itnlim=500, fixed=False, atol=0.0, btol=0.0,
+                            conlim=25.0)
+            f = infos[s * k + j]
+            assert (f["istop"], f["itn"]) == (io["istop"], io["itn"]), (s, j)
+            assert abs(f["acond"] - io["acond"]) <= 1e-10 * io["acond"], (s, j)
+            assert rel(Xg[c0:c1, j], xo) <= 1e-10, (s, j)
+    b.close()
+
+
 def test_batched_argument_errors():
     sh = SHAPES[1]
     sysd = synth.system(sh)

@@ -81,6 +81,10 @@ def test_lsqr_fixed_iterations_vs_oracle(cfg_small, k):
     tol_a = 1e-12 if k <= 10 else 1e-6
     assert abs(info["anorm"] - io["anorm"]) <= tol_a * io["anorm"]
     assert abs(info["znorm"] - io["znorm"]) <= 1e-10 * io["znorm"]
+    # condition estimate: the same sum of ||w_i / rho_i||^2; past convergence (~45 steps) its
+    # new terms are shaped by rounding like the variance estimate's
+    tol_c = 1e-10 if k <= 10 else 1e-3
+    assert abs(info["acond"] - io["acond"]) <= tol_c * io["acond"]
 
 
 @pytest.mark.parametrize("shape", SMALL_SHAPES, ids=lambda s: s.name)
@@ -354,3 +358,29 @@ def test_variance_estimate_converged_empty_columns_and_zero_rhs(cfg_small):
     assert info["istop"] == 4 and float(x2.abs().max()) == 0.0
     assert float(var2.abs().max()) == 0.0
     h2.close()
+
+
+@pytest.mark.parametrize("noise", [True, False], ids=["noisy", "exact"])
+@pytest.mark.parametrize("atol,btol,conlim", [(1e-8, 1e-8, 0.0), (0.0, 0.0, 30.0),
+                                              (0.0, 0.0, 0.0)],
+                         ids=["tolerances", "conlim", "machine_precision"])
+def test_stopping_rules_vs_oracle(noise, atol, btol, conlim):
+    """Every stopping test of Paige & Saunders: the same reason as the oracle at the same
+    step (the machine-precision tests compare quantities near rounding level: +-2 steps)."""
+    shape = SMALL_SHAPES[2]
+    sysd = synth.system(shape)
+    S = oracle_system(sysd)
+    h, _ = open_system(sysd)
+    b = S.aprod1(synth.x_true(shape)) + (synth.noise(shape) if noise else 0.0)
+    x = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    o = gsr.solve_opts(itnlim=2000, fixed_iters=False, atol=atol, btol=btol, conlim=conlim)
+    info = gsr.gsr_lsqr_solve(h, cuda(b), x, o)
+    xo, io = S.lsqr(b, itnlim=2000, fixed=False, atol=atol, btol=btol, conlim=conlim)
+    print(f"[stop] gpu itn {info['itn']} istop {info['istop']}; oracle itn {io['itn']} "
+          f"istop {io['istop']}", flush=True)
+    assert info["istop"] == io["istop"]
+    slack = 2 if (atol, btol, conlim) == (0.0, 0.0, 0.0) else 0
+    assert abs(info["itn"] - io["itn"]) <= slack
+    assert rel(host(x), xo) <= (1e-10 if info["itn"] == io["itn"] else 1e-8)
+    assert abs(info["acond"] - io["acond"]) <= 1e-3 * io["acond"]
+    h.close()
