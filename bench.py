@@ -52,6 +52,8 @@ def pass_bytes(m: int, n: int, shape, fused: bool, value_bytes: int = 8) -> dict
 def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
     """The oracle (single-threaded C) on the same system: per-iteration time from the
     difference of two fixed-iteration solves (setup of p excluded)."""
+    import numpy as np
+
     import oracle
 
     S = oracle.System(sysd["dims"], sysd["vals"], sysd["star"], sysd["att"], sysd["instr"])
@@ -62,10 +64,49 @@ def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
     S.lsqr(b, itnlim=iters_hi, fixed=True, p=p)
     t2 = time.perf_counter()
     per_it = ((t2 - t1) - (t1 - t0)) / (iters_hi - iters_lo)
+    # the two products on their own, once each
+    xr = np.random.default_rng(0).standard_normal(S.n)
+    t3 = time.perf_counter()
+    S.aprod1(xr)
+    t4 = time.perf_counter()
+    S.aprod2(b)
+    t5 = time.perf_counter()
     return {"value": 1.0 / per_it, "unit": "iterations/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters_hi - iters_lo} PC-LSQR iterations of the same {S.m}-row system "
                       f"(difference of {iters_hi}- and {iters_lo}-iteration solves, "
-                      f"{t2 - t0:.1f} s of CPU work)"}
+                      f"{t2 - t0:.1f} s of CPU work)",
+            "aprod1_s": round(t4 - t3, 4), "aprod2_s": round(t5 - t4, 4),
+            "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Device-to-device copy rate of this GPU (GB/s, read + write bytes), HIP events."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbps
 
 
 # ---- HBM traffic from rocprofv3 counters ---------------------------------------------
@@ -555,10 +596,12 @@ def main() -> None:
     for _ in range(args.warmup):
         gsr.gsr_lsqr_solve(h, b, x, opts)
     torch.cuda.synchronize()
-    infos = []
+    infos, step_s = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos.append(gsr.gsr_lsqr_solve(h, b, x, opts))
+        ts = time.perf_counter()
+        infos.append(gsr.gsr_lsqr_solve(h, b, x, opts))  # synchronizes
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     iters = sum(i["itn"] for i in infos)
@@ -582,8 +625,10 @@ def main() -> None:
                  else ("k_aprod1", "k_aprod2_star + k_reduce_partials + k_aprod2_att"))
         dom = 0 if ms1 >= ms2 else 1
         gb, msd = (gbps1, ms1) if dom == 0 else (gbps2, ms2)
+        copy_gbps = copy_bandwidth()
         roofline = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBPS, 4),
+                    "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(gb / copy_gbps, 4),
                     "traffic": stored_traffic(names[dom], shape.name,
                                               pb["pass1" if dom == 0 else "pass2"]),
                     "kernel": names[dom], "ms_per_launch": round(msd, 4),
@@ -614,6 +659,7 @@ def main() -> None:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step_median": round(1e3 * float(np.median(step_s)), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

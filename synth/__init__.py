@@ -207,7 +207,12 @@ S1M_O20 = Shape(1_000_000, 20, 20, 30_000, 6_000, seed=2, name="stars1e6_obs20_d
 #: 5e6 stars x 40 obs, N_DFA 100,000, 10,000 instrumental columns (2.0e8 rows, 25,310,001 cols).
 S5M_O40 = Shape(5_000_000, 40, 40, 100_000, 10_000, seed=3, name="stars5e6_obs40_dfa1e5_instr1e4")
 
-WORKLOADS = {s.name: s for s in (S1K_O60, S1M_O20, S5M_O40)}
+#: one GPU's share of the 2e8-row system split over 8 GPUs by star-aligned row blocks:
+#: 625,000 stars x 40 obs (2.5e7 rows) with the full attitude and instrumental widths.
+S625K_O40 = Shape(625_000, 40, 40, 100_000, 10_000, seed=101,
+                  name="stars625k_obs40_dfa1e5_instr1e4")
+
+WORKLOADS = {s.name: s for s in (S1K_O60, S1M_O20, S5M_O40, S625K_O40)}
 
 
 def batch_shapes(n_sys: int = 64, seed: int = 4, s_lo: float = 1e3, s_hi: float = 2e5,
