@@ -103,7 +103,7 @@ typedef struct gsr_solve_info {
                          6 / 7 / 8 the compatible, least-squares and condition tests with
                          the tolerances at machine precision (1 + t <= 1)                 */
     int32_t n_refine; /* outer steps taken (GSR_F32V), 1 otherwise                         */
-    int32_t reserved;
+    int32_t nonfinite; /* 1 if a non-finite value stopped the recurrence                    */
     double rnorm;     /* estimate of ||b - A x|| (last inner solve)                        */
     double arnorm;    /* estimate of ||(A D)^T r||                                         */
     double anorm;     /* Frobenius estimate of ||A D||                                      */
@@ -205,6 +205,24 @@ gsr_status gsr_lsqr_solve(gsr_handle *h, const double *b, double *x, const gsr_s
  */
 gsr_status gsr_lsqr_solve_var(gsr_handle *h, const double *b, double *x, double *var,
                               const gsr_solve_opts *opts, gsr_solve_info *info, void *stream);
+
+/*
+ * The binary64 PC-LSQR of gsr_lsqr_solve (Section 3, flowchart paragraph), stream-ordered:
+ * every launch goes to `stream`, in order, with no host synchronization, no allocation and
+ * no memset, so the call may be captured into a HIP graph (the graph then repeats the solve
+ * on the current contents of b).  All opts->itnlim iterations are enqueued one kernel at a
+ * time; once the device-side stop flag is set (fixed_iters = 0, or an exact breakdown) the
+ * remaining launches return at once.  When the stream reaches the end, x [n_cols] holds the
+ * solution and *info_dev (DEVICE memory, one gsr_solve_info) the solve information:
+ * ms_pass1 = ms_pass2 = 0 and n_pass = 0; a non-finite value sets info_dev->nonfinite
+ * instead of returning GSR_E_BREAKDOWN.  opts->precision must be GSR_F64 and opts->profile 0
+ * (GSR_E_UNSUPPORTED / GSR_E_INVAL otherwise).  The workspaces it uses belong to the handle
+ * and are allocated by gsr_lsqr_setup: calls on one handle must not overlap (nor overlap
+ * any other solve on the handle).
+ */
+gsr_status gsr_lsqr_solve_async(gsr_handle *h, const double *b, double *x,
+                                const gsr_solve_opts *opts, gsr_solve_info *info_dev,
+                                void *stream);
 
 /*
  * Adjoint of the least-squares solve, for a loss L(x*) with g = dL/dx* [n_cols]:

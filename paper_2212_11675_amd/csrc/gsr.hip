@@ -509,6 +509,7 @@ gsr_status read_info(gsr_handle* h, gsr_solve_info* info, hipStream_t s,
         info->itn = t.itn;
         info->istop = t.istop;
         info->n_refine = 1;
+        info->nonfinite = t.nonfinite;
         info->rnorm = t.rnorm;
         info->arnorm = t.arnorm;
         info->anorm = std::sqrt(t.anorm2);
@@ -558,6 +559,54 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
                        w.v, x, h->st, w.var, var_out);
     HIP_TRY(hipGetLastError());
     return read_info(h, info, s, prof);
+}
+
+// Solve information from the device state, written on the device (stream-ordered solve).
+static __global__ void k_write_info(const LsqrState* __restrict__ st, gsr_solve_info* info,
+                                    int32_t fused) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    gsr_solve_info f = {};
+    f.itn = st->itn;
+    f.istop = st->istop;
+    f.n_refine = 1;
+    f.nonfinite = st->nonfinite;
+    f.rnorm = st->rnorm;
+    f.arnorm = st->arnorm;
+    f.anorm = sqrt(st->anorm2);
+    f.znorm = sqrt(st->znorm2);
+    f.bnorm = st->bnorm;
+    f.fused = fused;
+    f.acond = sqrt(st->anorm2) * sqrt(st->ddnorm);
+    *info = f;
+}
+
+// The binary64 PC-LSQR with every iteration launched on `s` (no graph of its own, no host
+// synchronization, no allocation): capturable into the caller's graph.
+gsr_status fwd_solve_async(gsr_handle* h, const double* b, double* x, const gsr_solve_opts& o,
+                           gsr_solve_info* info_dev, hipStream_t s) {
+    const Geo& g = h->g;
+    LsqrWork& w = h->fwd64;
+    const double* p = h->p64;
+    hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
+                       w.u, nullptr, h->partA);
+    hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gm,
+                       o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim);
+    fill(h->s, g.n, 0.0, s);
+    if (h->fused)
+        launch_fused<double, false, true>(h, h->vals, h->attT64, w.u, h->s, h->partB, s,
+                                          nullptr);
+    else
+        launch_aprod2<double, A2_LSQR>(h, h->vals, h->attT64, w.u, h->s, s);
+    hipLaunchKernelGGL((k_vec_v<true>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v,
+                       w.w, w.z, h->xt, h->st, h->partB, nullptr);
+    hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
+    for (int it = 0; it < o.itnlim; ++it)
+        fwd_iteration<double>(h, w, h->vals, h->attT64, p, s);
+    hipLaunchKernelGGL((k_final<true>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, p, w.z, w.w, w.v,
+                       x, h->st);
+    hipLaunchKernelGGL(k_write_info, dim3(1), dim3(64), 0, s, h->st, info_dev, (int32_t)h->fused);
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
 }
 
 gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_solve_opts& o,
@@ -744,6 +793,9 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
                        GSR_OK)
         return bail(st);
     if ((st = dalloc(&h->st, 1)) != GSR_OK) return bail(st);
+    // the binary64 solve's vectors: allocated here so that a stream-ordered solve allocates
+    // nothing
+    if ((st = ensure_work(h->fwd64, g.m, g.n)) != GSR_OK) return bail(st);
     {
         hipError_t e = hipMemsetAsync(h->st, 0, sizeof(LsqrState), s);
         if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
@@ -981,6 +1033,20 @@ gsr_status gsr_lsqr_solve_var(gsr_handle* h, const double* b, double* x, double*
     GSR_TRY(set_device(h));
     return fwd_solve<double, true>(h, h->fwd64v, h->vals, h->attT64, h->p64, b, x, o, info,
                                    as_stream(stream), var);
+}
+
+gsr_status gsr_lsqr_solve_async(gsr_handle* h, const double* b, double* x,
+                                const gsr_solve_opts* opts, gsr_solve_info* info_dev,
+                                void* stream) {
+    g_last_error.clear();
+    if (!h || !x || !info_dev || (!b && h->g.m > 0)) return fail(GSR_E_INVAL, "null argument");
+    const gsr_solve_opts o = opts ? *opts : default_opts();
+    GSR_TRY(check_opts(o));
+    if (o.precision != GSR_F64)
+        return fail(GSR_E_UNSUPPORTED, "the stream-ordered solve is binary64 only");
+    if (o.profile) return fail(GSR_E_INVAL, "profile needs host synchronization");
+    GSR_TRY(set_device(h));
+    return fwd_solve_async(h, b, x, o, info_dev, as_stream(stream));
 }
 
 gsr_status gsr_lsqr_solve_adjoint(gsr_handle* h, const double* gvec, double* mu, double* lam,

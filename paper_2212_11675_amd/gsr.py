@@ -28,7 +28,7 @@ EXPORTS = (
     "gsr_abi_version", "gsr_status_string", "gsr_last_error", "gsr_lsqr_setup", "gsr_destroy",
     "gsr_get_size", "gsr_aprod1", "gsr_aprod2", "gsr_aprod1_f32v", "gsr_aprod2_f32v",
     "gsr_precond", "gsr_residual", "gsr_lsqr_solve", "gsr_lsqr_solve_var",
-    "gsr_lsqr_solve_adjoint", "gsr_grad_vals",
+    "gsr_lsqr_solve_async", "gsr_lsqr_solve_adjoint", "gsr_grad_vals",
     "gsr_batch_setup", "gsr_batch_destroy", "gsr_batch_col_offsets", "gsr_batch_aprod1",
     "gsr_batch_aprod2", "gsr_batch_solve",
 )
@@ -61,7 +61,7 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("itn", ctypes.c_int32), ("istop", ctypes.c_int32),
-                ("n_refine", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_refine", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
                 ("rnorm", ctypes.c_double), ("arnorm", ctypes.c_double),
                 ("anorm", ctypes.c_double), ("znorm", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("ms_pass1", ctypes.c_double),
@@ -69,7 +69,7 @@ class SolveInfo(ctypes.Structure):
                 ("fused", ctypes.c_int32), ("acond", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -104,6 +104,7 @@ def load() -> ctypes.CDLL:
                                 ctypes.POINTER(SolveInfo), vp]),
         "gsr_lsqr_solve_var": (st, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                     ctypes.POINTER(SolveInfo), vp]),
+        "gsr_lsqr_solve_async": (st, [vp, vp, vp, ctypes.POINTER(SolveOpts), vp, vp]),
         "gsr_lsqr_solve_adjoint": (st, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                         ctypes.POINTER(SolveInfo), vp]),
         "gsr_grad_vals": (st, [vp, vp, vp, vp, vp, vp, vp]),
@@ -257,6 +258,29 @@ def gsr_lsqr_solve_var(h: Handle, b, x, var, opts: SolveOpts | None = None,
                                      ctypes.byref(opts) if opts is not None else None,
                                      ctypes.byref(info), _stream(stream)), "gsr_lsqr_solve_var")
     return info.as_dict()
+
+
+def solve_info_buffer(device="cuda") -> torch.Tensor:
+    """Device memory for one gsr_solve_info (the output of gsr_lsqr_solve_async)."""
+    return torch.zeros(ctypes.sizeof(SolveInfo), dtype=torch.uint8, device=device)
+
+
+def read_solve_info(buf: torch.Tensor) -> dict:
+    """Copy a device gsr_solve_info to the host (synchronizes with buf's producer)."""
+    host_bytes = buf.cpu().numpy().tobytes()
+    return SolveInfo.from_buffer_copy(host_bytes).as_dict()
+
+
+def gsr_lsqr_solve_async(h: Handle, b, x, info_dev, opts: SolveOpts | None = None,
+                         stream=None) -> None:
+    """Stream-ordered binary64 PC-LSQR: no synchronization, capturable into a graph; the
+    solve information lands in info_dev (see solve_info_buffer / read_solve_info)."""
+    _check(load().gsr_lsqr_solve_async(h.ptr, _dev(b, torch.float64, h.m, "b"),
+                                       _dev(x, torch.float64, h.n, "x"),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       _dev(info_dev, torch.uint8, ctypes.sizeof(SolveInfo),
+                                            "info_dev"),
+                                       _stream(stream)), "gsr_lsqr_solve_async")
 
 
 def gsr_lsqr_solve_adjoint(h: Handle, g, mu, lam, opts: SolveOpts | None = None,

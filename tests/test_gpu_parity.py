@@ -384,3 +384,47 @@ def test_stopping_rules_vs_oracle(noise, atol, btol, conlim):
     assert rel(host(x), xo) <= (1e-10 if info["itn"] == io["itn"] else 1e-8)
     assert abs(info["acond"] - io["acond"]) <= 1e-3 * io["acond"]
     h.close()
+
+
+def test_stream_ordered_solve_and_graph_capture(cfg_small):
+    """gsr_lsqr_solve_async: the same solve as gsr_lsqr_solve with the information left in
+    device memory; captured into a graph and replayed on new right-hand sides, with eager
+    solves and synchronizations between the replays, every replay matching the eager solve
+    and the oracle."""
+    c = cfg_small
+    S, h = c["S"], c["h"]
+    o = gsr.solve_opts(itnlim=60, fixed_iters=False, atol=1e-12, btol=1e-12)
+    xs = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    ref = gsr.gsr_lsqr_solve(h, cuda(c["b"]), xs, o)
+    x = torch.empty_like(xs)
+    info = gsr.solve_info_buffer()
+    gsr.gsr_lsqr_solve_async(h, cuda(c["b"]), x, info, o)
+    f = gsr.read_solve_info(info)
+    assert (f["itn"], f["istop"], f["nonfinite"]) == (ref["itn"], ref["istop"], 0)
+    assert rel(host(x), host(xs)) <= 1e-12
+    for key in ("rnorm", "arnorm", "anorm", "znorm", "bnorm", "acond"):
+        assert abs(f[key] - ref[key]) <= 1e-10 * abs(ref[key]), key
+    with pytest.raises(gsr.GsrError):
+        gsr.gsr_lsqr_solve_async(h, cuda(c["b"]), x, info, gsr.solve_opts(profile=True))
+
+    bg = cuda(c["b"])
+    xg = torch.empty_like(xs)
+    infog = gsr.solve_info_buffer()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gsr.gsr_lsqr_solve_async(h, bg, xg, infog, o)
+    rng = np.random.default_rng(41)
+    for rep in range(3):
+        print(f"[graph] replay {rep}", flush=True)
+        bnew = S.aprod1(rng.standard_normal(S.n)) + 1e-3 * rng.standard_normal(S.m)
+        bg.copy_(cuda(bnew))
+        g.replay()
+        torch.cuda.synchronize()
+        fg = gsr.read_solve_info(infog)
+        xe = torch.empty_like(xs)
+        ie = gsr.gsr_lsqr_solve(h, cuda(bnew), xe, o)
+        assert (fg["itn"], fg["istop"]) == (ie["itn"], ie["istop"]), rep
+        assert rel(host(xg), host(xe)) <= 1e-12, rep
+        xo, _ = S.lsqr(bnew, itnlim=fg["itn"], fixed=True)
+        assert rel(host(xg), xo) <= 1e-10, rep
