@@ -312,13 +312,25 @@ __device__ __forceinline__ void st_r(double* __restrict__ p, const double (&v)[R
     }
 }
 
+// The three coefficient pairs m[] held by quad lane CTRL / 0x55, broadcast to the whole quad
+// as six doubles (quad_perm [s,s,s,s] = s * 0x55).
+template <int CTRL>
+__device__ __forceinline__ void bcast_pairs(const f64x2 (&m)[3], double* __restrict__ out) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        out[2 * i] = dpp_f64<CTRL>(m[i].x);
+        out[2 * i + 1] = dpp_f64<CTRL>(m[i].y);
+    }
+}
+
 // Fused batched row pass: for every (row, rhs j) of a block chunk
 //   U[r, j] = sv_j (A XT)[r, j] - alpha_j su_j U[r, j]
 // and S += A^T U (astrometric: run accumulators; instrumental/global: LDS of the current
 // system), reading each row once.  Sum U^2 per (block chunk, j) -> partials.
 // Lane layout: L = min(K, 4) lanes per row, each lane R = K / L right-hand sides, so one row
-// costs 16-byte loads: the row's coefficients (all L lanes read the same 192 bytes), and per
-// column the lane's R consecutive values of the K-column block (RHS-minor storage).
+// costs 16-byte loads: the row's coefficients (with L = 4 each lane reads a quarter and the
+// quad exchanges them; otherwise all L lanes read the same 192 bytes), and per column the
+// lane's R consecutive values of the K-column block (RHS-minor storage).
 // Pairs that have stopped keep their U unchanged and contribute nothing.
 template <typename VT, int K>
 static __global__ __launch_bounds__(512) void k_baprod12(
@@ -387,6 +399,12 @@ static __global__ __launch_bounds__(512) void k_baprod12(
             ys[i] = ps->alpha * ps->su;
             any_live = any_live || live[i];
         }
+        if constexpr (L == 4) {
+            // the quad of a row shares its loads: it goes through the row while any pair of
+            // the system is live (a lane whose own pairs have stopped adds zeros)
+#pragma unroll
+            for (int j = 0; j < K; ++j) any_live = any_live || !st[(int64_t)cur * K + j].stop;
+        }
         const int64_t len = c.e1 - c.e0;
         const int64_t sub = ((len + wpb - 1) / wpb + RS - 1) / RS * RS;
         const int64_t r_beg = min(c.e1, c.e0 + w * sub), r_end = min(c.e1, r_beg + sub);
@@ -436,19 +454,50 @@ static __global__ __launch_bounds__(512) void k_baprod12(
                 const int64_t tile = d.btile0 + lr / kStepRows;
                 const int rgl = (int)(lr % kStepRows);
                 double a[kPar];
+                int32_t sr, tr, ins[kInstr];
                 const f64x2* vp = reinterpret_cast<const f64x2*>(vt + tile * kBTileVals) + rgl;
+                const int32_t* ip = it + tile * kBTileIdx + rgl * 8;
+                if constexpr (L == 4) {
+                    // the row's quad splits its loads (lane q: coefficient pairs 3q..3q+2 and
+                    // index slots 2q, 2q+1) and exchanges them with DPP quad broadcasts
+                    const int q = lane & 3;
+                    const f64x2 m[3] = {__builtin_nontemporal_load(vp + (3 * q) * kStepRows),
+                                        __builtin_nontemporal_load(vp + (3 * q + 1) * kStepRows),
+                                        __builtin_nontemporal_load(vp + (3 * q + 2) * kStepRows)};
+                    const i32x2 iv =
+                        __builtin_nontemporal_load(reinterpret_cast<const i32x2*>(ip) + q);
+                    bcast_pairs<0x00>(m, a + 0);
+                    bcast_pairs<0x55>(m, a + 6);
+                    bcast_pairs<0xAA>(m, a + 12);
+                    bcast_pairs<0xFF>(m, a + 18);
+                    sr = __builtin_amdgcn_update_dpp(0, iv.x, 0x00, 0xF, 0xF, false);
+                    tr = __builtin_amdgcn_update_dpp(0, iv.y, 0x00, 0xF, 0xF, false);
+                    ins[0] = __builtin_amdgcn_update_dpp(0, iv.x, 0x55, 0xF, 0xF, false);
+                    ins[1] = __builtin_amdgcn_update_dpp(0, iv.y, 0x55, 0xF, 0xF, false);
+                    ins[2] = __builtin_amdgcn_update_dpp(0, iv.x, 0xAA, 0xF, 0xF, false);
+                    ins[3] = __builtin_amdgcn_update_dpp(0, iv.y, 0xAA, 0xF, 0xF, false);
+                    ins[4] = __builtin_amdgcn_update_dpp(0, iv.x, 0xFF, 0xF, 0xF, false);
+                    ins[5] = __builtin_amdgcn_update_dpp(0, iv.y, 0xFF, 0xF, 0xF, false);
+                } else {
 #pragma unroll
-                for (int k = 0; k < kPar / 2; ++k) {
-                    const f64x2 t = __builtin_nontemporal_load(vp + k * kStepRows);
-                    a[2 * k] = t.x;
-                    a[2 * k + 1] = t.y;
+                    for (int k = 0; k < kPar / 2; ++k) {
+                        const f64x2 t = __builtin_nontemporal_load(vp + k * kStepRows);
+                        a[2 * k] = t.x;
+                        a[2 * k + 1] = t.y;
+                    }
+                    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+                    const i32x4* ip4 = reinterpret_cast<const i32x4*>(ip);
+                    const i32x4 i0 = __builtin_nontemporal_load(ip4);
+                    const i32x4 i1 = __builtin_nontemporal_load(ip4 + 1);
+                    sr = i0.x;
+                    tr = i0.y;
+                    ins[0] = i0.z;
+                    ins[1] = i0.w;
+                    ins[2] = i1.x;
+                    ins[3] = i1.y;
+                    ins[4] = i1.z;
+                    ins[5] = i1.w;
                 }
-                typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-                const i32x4* ip = reinterpret_cast<const i32x4*>(it + tile * kBTileIdx + rgl * 8);
-                const i32x4 i0 = __builtin_nontemporal_load(ip);
-                const i32x4 i1 = __builtin_nontemporal_load(ip + 1);
-                const int32_t sr = i0.x, tr = i0.y;
-                const int32_t ins[kInstr] = {i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
                 double sum[R], xv_[R];
 #pragma unroll
                 for (int i = 0; i < R; ++i) sum[i] = 0.0;
