@@ -565,16 +565,62 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     if (cur >= 0) flush_lds();
 }
 
-// Attitude pass over the t-ordered copy (each system's rows keep their own range).  Lane
-// layout as in k_baprod12: L = min(K, 4) lanes per row, R = K / L right-hand sides per lane;
-// each lane reads the row's 12 attitude coefficients (16-byte loads) and its R values of Y.
+// Run accumulation as run_step (keys sorted within a wave step, -1 for rows that take no
+// part), with the step's values produced on demand by val(j) and each finished run's sum
+// passed on as soon as it is reduced, flush1(key, j, sum): neither the step's values nor the
+// reduced sums are held as arrays, which keeps the attitude pass at a few waves per SIMD.
+template <int NV, int STRIDE, typename V, typename F>
+__device__ __forceinline__ void run_step_lean(int32_t key, V&& val, double (&acc)[NV],
+                                              int32_t& ckey, F&& flush1) {
+    const uint64_t valid = __ballot(key >= 0);
+    if (valid == 0) return;
+    const int32_t kfirst =
+        __builtin_amdgcn_readlane(key, __ffsll((unsigned long long)valid) - 1);
+    const int32_t klast = __builtin_amdgcn_readlane(key, 63 - __clzll((unsigned long long)valid));
+    if (kfirst == ckey && klast == ckey) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] += val(j);
+        return;
+    }
+    if (ckey >= 0) {  // the open run ends in this step (or ended at its start)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            flush1(ckey, j, group_sum<STRIDE>(acc[j] + (key == ckey ? val(j) : 0.0)));
+    }
+    auto next_after = [&](int32_t k) {
+        const uint64_t gt = __ballot(key > k);
+        return (int32_t)__builtin_amdgcn_readlane(key, __ffsll((unsigned long long)gt) - 1);
+    };
+    int32_t k = (kfirst == ckey) ? next_after(ckey) : kfirst;
+    while (k != klast) {  // runs that start and end inside the step
+#pragma unroll
+        for (int j = 0; j < NV; ++j) flush1(k, j, group_sum<STRIDE>(key == k ? val(j) : 0.0));
+        k = next_after(k);
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = (key == klast) ? val(j) : 0.0;
+    ckey = klast;
+}
+
+template <int NV, int STRIDE, typename F>
+__device__ __forceinline__ void run_close_lean(double (&acc)[NV], int32_t& ckey, F&& flush1) {
+    if (ckey < 0) return;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) flush1(ckey, j, group_sum<STRIDE>(acc[j]));
+    ckey = -1;
+}
+
+// Attitude pass over the t-ordered copy (each system's rows keep their own range).  One lane
+// per right-hand side (L = K lanes per row, R = 1): each lane reads the row's 12 attitude
+// coefficients (16-byte loads) and its value of Y; with one right-hand side per lane the run
+// accumulators stay small enough for four waves per SIMD.
 template <typename VT, int MODE, int K>
 static __global__ __launch_bounds__(256) void k_baprod2_att(
     const SysDesc* __restrict__ sys, const Seg* __restrict__ chunks, int nchunks,
     const VT* __restrict__ attT, const int32_t* __restrict__ rowT,
     const int32_t* __restrict__ tT, const double* __restrict__ Y, double* __restrict__ X,
     const LsqrState* __restrict__ st) {
-    constexpr int L = K >= 4 ? 4 : K;
+    constexpr int L = K;
     constexpr int R = K / L;
     constexpr int RS = kWave / L;
     constexpr int NA = kAxes * kParAxis;
@@ -593,18 +639,10 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
         }
         // (A2_LSQR: u~ unnormalized; k_bvec_v applies 1/beta)
         double* __restrict__ Xt = X + (d.col0 + d.att0) * K + j0;
-        auto flush = [&](int32_t key, const double (&t)[NA * R]) {
-            if (rr != 0) return;
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                if (!live[i]) continue;
-#pragma unroll
-                for (int ax = 0; ax < kAxes; ++ax)
-#pragma unroll
-                    for (int q = 0; q < kParAxis; ++q)
-                        atomic_add_f64(Xt + ((int64_t)ax * d.T + key + q) * K + i,
-                                       t[i * NA + ax * kParAxis + q]);
-            }
+        // value j = i * NA + ax * kParAxis + q: right-hand side i, column t + q of axis ax
+        auto flush1 = [&](int32_t key, int j, double t) {
+            const int i = j / NA, ax = (j % NA) / kParAxis, q = j % kParAxis;
+            if (rr == 0 && live[i]) atomic_add_f64(Xt + ((int64_t)ax * d.T + key + q) * K + i, t);
         };
         double acc[NA * R];
 #pragma unroll
@@ -614,12 +652,13 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
             const int64_t k = k0 + rr;
             const bool valid = any_live && k < c.e1;
             int32_t key = -1;
-            double v[NA * R];
+            double yy[R], a[NA];
 #pragma unroll
-            for (int q = 0; q < NA * R; ++q) v[q] = 0.0;
+            for (int i = 0; i < R; ++i) yy[i] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NA; ++q) a[q] = 0.0;
             if (valid) {
                 key = tT[k];
-                double yy[R];
                 if (MODE == A2_SQ) {
 #pragma unroll
                     for (int i = 0; i < R; ++i) yy[i] = 0.0;
@@ -628,7 +667,6 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
 #pragma unroll
                     for (int i = 0; i < R; ++i) yy[i] = live[i] ? yy[i] : 0.0;
                 }
-                double a[NA];
                 {  // the row's attitude tile
                     const int64_t lr = k - d.row0;
                     const int64_t tile = d.btile0 + lr / kStepRows;
@@ -641,14 +679,11 @@ static __global__ __launch_bounds__(256) void k_baprod2_att(
                         a[2 * q + 1] = t.y;
                     }
                 }
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-#pragma unroll
-                    for (int q = 0; q < NA; ++q) v[i * NA + q] = contrib<MODE>(a[q], yy[i]);
             }
-            run_step<NA * R, L>(key, v, acc, ckey, flush);
+            auto val = [&](int j) { return contrib<MODE>(a[j % NA], yy[j / NA]); };
+            run_step_lean<NA * R, L>(key, val, acc, ckey, flush1);
         }
-        run_close<NA * R, L>(acc, ckey, flush);
+        run_close_lean<NA * R, L>(acc, ckey, flush1);
     }
 }
 
