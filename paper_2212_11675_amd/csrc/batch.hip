@@ -346,8 +346,14 @@ static __global__ __launch_bounds__(512) void k_baprod12(
     constexpr int RS = kWave / L;
     const int lane = threadIdx.x % kWave, rr = lane / L, j0 = (lane % L) * R;
     const int w = threadIdx.x / kWave, wpb = blockDim.x / kWave;
-    const int per = (nbchunks + gridDim.x - 1) / gridDim.x;
-    const int bc_beg = xcd_block(blockIdx.x, gridDim.x) * per, bc_end = min(nbchunks, bc_beg + per);
+    // Each XCD takes an eighth of the block chunks (in system order) and deals them to its
+    // blocks in turn, so that its blocks move through the systems together and share each
+    // system's attitude columns in the XCD's L2 (consecutive blocks go to consecutive XCDs).
+    const int ngrp = min((int)gridDim.x, kXcd);
+    const int grp = blockIdx.x % ngrp, gi = blockIdx.x / ngrp;
+    const int nbg = gridDim.x / ngrp + (grp < (int)gridDim.x % ngrp ? 1 : 0);
+    const int bc_beg = (int)((int64_t)nbchunks * grp / ngrp);
+    const int bc_end = (int)((int64_t)nbchunks * (grp + 1) / ngrp);
     const int nl = (max_instr + 1) * K;
     double* lusq = lds + nl;
     double* lxi = lusq + K;
@@ -377,7 +383,7 @@ static __global__ __launch_bounds__(512) void k_baprod12(
         }
         __syncthreads();
     };
-    for (int bc = bc_beg; bc < bc_end; ++bc) {
+    for (int bc = bc_beg + gi; bc < bc_end; bc += nbg) {
         const Seg c = bchunks[bc];
         if (c.sys != cur) {
             if (cur >= 0) flush_lds();
