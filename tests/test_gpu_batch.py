@@ -36,7 +36,7 @@ def make_batch(shapes, k):
     return b, systems, dev
 
 
-@pytest.mark.parametrize("k", [1, 2, 8])
+@pytest.mark.parametrize("k", [1, 2, 4, 8])
 def test_batched_products_vs_oracle(k):
     print(f"[batch products] k={k}", flush=True)
     b, systems, _ = make_batch(SHAPES, k)
@@ -62,7 +62,7 @@ def test_batched_products_vs_oracle(k):
     b.close()
 
 
-@pytest.mark.parametrize("k,iters", [(8, 1), (8, 7), (8, 40), (2, 15)])
+@pytest.mark.parametrize("k,iters", [(8, 1), (8, 7), (8, 40), (4, 12), (2, 15), (1, 9)])
 def test_batched_solve_matches_solo_oracle(k, iters):
     print(f"[batch solve] k={k} iters={iters}", flush=True)
     b, systems, _ = make_batch(SHAPES, k)
