@@ -266,7 +266,8 @@ def solve_info_buffer(device="cuda") -> torch.Tensor:
 
 
 def read_solve_info(buf: torch.Tensor) -> dict:
-    """Copy a device gsr_solve_info to the host (synchronizes with buf's producer)."""
+    """Copy a device gsr_solve_info to the host.  The copy is ordered on torch's current
+    stream: if the solve ran on another stream, synchronize that stream first."""
     host_bytes = buf.cpu().numpy().tobytes()
     return SolveInfo.from_buffer_copy(host_bytes).as_dict()
 
