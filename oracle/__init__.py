@@ -82,8 +82,8 @@ def _load():
         lib.or_residual.restype = None
         lib.or_residual.argtypes = [pd, vp, vp, vp, vp, vp, vp, vp]
         lib.or_refine.restype = i32
-        lib.or_refine.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, f64, i32, i32, f64, f64, vp,
-                                  vp]
+        lib.or_refine.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, f64, i32, i32, i32, f64, f64,
+                                  vp, vp]
         lib.or_grad_vals.restype = None
         lib.or_grad_vals.argtypes = [pd, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = lib
@@ -215,16 +215,19 @@ class System:
         return r
 
     def refine(self, b, vals_lo, max_outer=5, refine_tol=1e-10, inner_itnlim=200,
-               inner_fixed=False, inner_atol=1e-14, inner_btol=1e-14):
+               inner_fixed=False, inner_atol=1e-14, inner_btol=1e-14, later_itnlim=0):
         """Mixed-precision residual correction; vals_lo = binary32-rounded coefficients
-        (any float array; widened exactly to double).  Returns (x, outer, inner_itns)."""
+        (any float array; widened exactly to double); the correction solves after the first
+        take later_itnlim iterations at most (0: inner_itnlim).  Returns (x, outer,
+        inner_itns)."""
         b = _f64(b)
         lo = np.ascontiguousarray(np.asarray(vals_lo, dtype=np.float32).astype(np.float64))
         x = np.empty(self.n)
         inner = np.zeros(max(max_outer, 1), dtype=np.int32)
         k = _load().or_refine(ctypes.byref(self.d), _p(self.vals), _p(lo), _p(self.star),
                               _p(self.att), _p(self.instr), _p(b), int(max_outer),
-                              float(refine_tol), int(inner_itnlim), int(bool(inner_fixed)),
+                              float(refine_tol), int(inner_itnlim), int(later_itnlim),
+                              int(bool(inner_fixed)),
                               float(inner_atol), float(inner_btol), _p(x), _p(inner))
         return x, int(k), inner[:k].tolist()
 

@@ -423,13 +423,15 @@ void or_residual(const or_dims *d, const double *vals, const int32_t *star, cons
  *   x_0 = 0, r_0 = b;  for k = 0, 1, ...:  d_k = PC-LSQR(A_lo, r_k) with p_lo from A_lo,
  *   x_{k+1} = x_k + d_k; stop when ||d_k|| <= refine_tol ||x_{k+1}||;
  *   otherwise r_{k+1} = b - A x_{k+1} with the double-precision coefficients.
+ * The first inner solve takes at most inner_itnlim iterations, the later ones (which only
+ * correct an error at the binary32 level) at most later_itnlim (0: inner_itnlim).
  * Returns the number of outer steps; inner iteration counts go to inner_itn[k].
  */
 int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
                   const int32_t *star, const int32_t *att, const int32_t *instr,
                   const double *b, int32_t max_outer, double refine_tol, int32_t inner_itnlim,
-                  int32_t inner_fixed, double inner_atol, double inner_btol, double *x,
-                  int32_t *inner_itn)
+                  int32_t later_itnlim, int32_t inner_fixed, double inner_atol,
+                  double inner_btol, double *x, int32_t *inner_itn)
 {
     const int64_t m = d->n_rows, n = or_n_cols(d);
     double *p_lo = malloc((size_t)n * sizeof(double));
@@ -441,7 +443,9 @@ int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
     int32_t k = 0;
     while (k < max_outer) {
         or_info info;
-        or_pclsqr(d, vals_lo, star, att, instr, p_lo, r, inner_itnlim, inner_fixed, inner_atol,
+        /* the correction solves after the first may take a shorter iteration limit */
+        const int32_t itnlim = (k > 0 && later_itnlim > 0) ? later_itnlim : inner_itnlim;
+        or_pclsqr(d, vals_lo, star, att, instr, p_lo, r, itnlim, inner_fixed, inner_atol,
                   inner_btol, 0.0, dx, &info, NULL);
         if (inner_itn)
             inner_itn[k] = info.itn;

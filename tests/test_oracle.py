@@ -341,6 +341,29 @@ def test_refine_reaches_fp64_solution():
     assert np.linalg.norm(xr0 - xt) <= 1e-12 * np.linalg.norm(xt)
 
 
+def test_refine_schedule_with_short_correction_solves():
+    """A first inner solve of k1 steps, then correction solves of k2 steps: the composition
+    written out with scipy's sparse residual, and the binary64 solution reached with short
+    corrections."""
+    shape = synth.S1K_O60
+    s, S = _system(shape)
+    A = csr(s["dims"], s["vals"], s["star"], s["att"], s["instr"])
+    b = A @ synth.x_true(shape) + synth.noise(shape)
+    lo = s["vals"].astype(np.float32)
+    S32 = S.with_vals(lo.astype(np.float64))
+    x1, _ = S32.lsqr(b, itnlim=30, fixed=True)
+    d1, _ = S32.lsqr(b - A @ x1, itnlim=6, fixed=True)
+    xr, outer, inner = S.refine(b, lo, max_outer=2, refine_tol=0.0, inner_itnlim=30,
+                                later_itnlim=6, inner_fixed=True)
+    assert (outer, inner) == (2, [30, 6])
+    assert np.linalg.norm(xr - (x1 + d1)) <= 1e-13 * np.linalg.norm(xr)
+    x64, _ = S.lsqr(b, itnlim=300, fixed=False, atol=1e-15, btol=1e-15)
+    xr, outer, inner = S.refine(b, lo, max_outer=3, refine_tol=0.0, inner_itnlim=300,
+                                later_itnlim=12, inner_atol=1e-12, inner_btol=1e-12)
+    assert inner[0] > 12 and all(k <= 12 for k in inner[1:])
+    assert np.linalg.norm(xr - x64) <= 1e-9 * np.linalg.norm(x64)
+
+
 def test_refine_with_exact_low_precision_is_one_solve():
     shape = synth.Shape(10, 20, 20, 10, 12, seed=15)
     s, S = _system(shape)
