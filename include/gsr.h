@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 2
+#define GSR_ABI_VERSION 3
 
 typedef enum gsr_status {
     GSR_OK = 0,
@@ -94,6 +94,9 @@ typedef struct gsr_solve_opts {
                             acond of A D reaches conlim (0 = no limit).  After the atol /
                             btol and conlim tests, Paige & Saunders' three tests at
                             machine precision also stop the iteration (istop 6, 7, 8)    */
+    int32_t refine_itnlim; /* GSR_F32V: iteration limit of the correction solves after the
+                            first (0 = itnlim); they only remove a binary32-level error  */
+    int32_t reserved;
 } gsr_solve_opts;
 
 typedef struct gsr_solve_info {

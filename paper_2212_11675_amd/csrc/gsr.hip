@@ -662,6 +662,7 @@ gsr_status check_opts(const gsr_solve_opts& o) {
     if (o.itnlim < 0) return fail(GSR_E_INVAL, "itnlim < 0");
     if (!(o.atol >= 0) || !(o.btol >= 0)) return fail(GSR_E_INVAL, "atol/btol must be >= 0");
     if (!(o.conlim >= 0)) return fail(GSR_E_INVAL, "conlim must be >= 0");
+    if (o.refine_itnlim < 0) return fail(GSR_E_INVAL, "refine_itnlim < 0");
     if (o.precision != GSR_F64 && o.precision != GSR_F32V)
         return fail(GSR_E_INVAL, "unknown precision %d", o.precision);
     if (o.precision == GSR_F32V && o.max_refine < 1) return fail(GSR_E_INVAL, "max_refine < 1");
@@ -992,7 +993,9 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
     hipError_t e = hipSuccess;
     gsr_status rc = GSR_OK;
     while (k < o.max_refine) {
-        rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx, o, &inner,
+        gsr_solve_opts ok = o;
+        if (k > 0 && o.refine_itnlim > 0) ok.itnlim = o.refine_itnlim;
+        rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx, ok, &inner,
                               s);
         if (rc != GSR_OK) break;
         total_itn += inner.itn;

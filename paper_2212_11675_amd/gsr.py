@@ -14,7 +14,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsr.so")
-ABI_VERSION = 2  # GSR_ABI_VERSION of include/gsr.h
+ABI_VERSION = 3  # GSR_ABI_VERSION of include/gsr.h
 
 GSR_F64 = 0
 GSR_F32V = 1
@@ -56,7 +56,8 @@ class SolveOpts(ctypes.Structure):
                 ("atol", ctypes.c_double), ("btol", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("conlim", ctypes.c_double)]
+                ("profile", ctypes.c_int32), ("conlim", ctypes.c_double),
+                ("refine_itnlim", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -158,10 +159,10 @@ def make_dims(n_rows, n_stars, n_dfa, n_instr, n_glob=1) -> Dims:
 
 def solve_opts(itnlim=100, fixed_iters=True, atol=1e-14, btol=1e-14, precision=GSR_F64,
                max_refine=4, refine_tol=1e-10, check_every=16, profile=False,
-               conlim=0.0) -> SolveOpts:
+               conlim=0.0, refine_itnlim=0) -> SolveOpts:
     return SolveOpts(int(itnlim), int(bool(fixed_iters)), float(atol), float(btol),
                      int(precision), int(max_refine), float(refine_tol), int(check_every),
-                     int(bool(profile)), float(conlim))
+                     int(bool(profile)), float(conlim), int(refine_itnlim), 0)
 
 
 class Handle:

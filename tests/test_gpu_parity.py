@@ -134,6 +134,17 @@ def test_mixed_precision_refinement(cfg_small):
                                  refine_tol=1e-10, inner_itnlim=300, inner_atol=1e-12,
                                  inner_btol=1e-12)
     assert rel(xr, xro) <= 1e-8
+    # schedule: a first inner solve of 30 steps, then a correction solve of 6 (fixed counts),
+    # against the oracle's refinement with the same schedule
+    o2 = gsr.solve_opts(itnlim=30, fixed_iters=True, precision=gsr.GSR_F32V, max_refine=2,
+                        refine_tol=0.0, refine_itnlim=6)
+    info2 = gsr.gsr_lsqr_solve(c["h"], cuda(c["b"]), x, o2)
+    assert (info2["itn"], info2["n_refine"]) == (36, 2)
+    xso, outer, inner = S.refine(c["b"], c["sysd"]["vals"].astype(np.float32), max_outer=2,
+                                 refine_tol=0.0, inner_itnlim=30, later_itnlim=6,
+                                 inner_fixed=True)
+    assert (outer, inner) == (2, [30, 6])
+    assert rel(host(x), xso) <= 1e-10
     # one inner solve only (no refinement): the binary32 floor is visible and reported
     o1 = gsr.solve_opts(itnlim=300, fixed_iters=False, atol=1e-12, btol=1e-12,
                         precision=gsr.GSR_F32V, max_refine=1)
