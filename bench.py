@@ -548,7 +548,7 @@ def main() -> None:
                     help="replay the captured iteration graph instead of event-bracketed launches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU split of the path is a design note, not a measured configuration",
               file=sys.stderr)
         sys.exit(2)

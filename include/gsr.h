@@ -47,7 +47,7 @@ typedef enum gsr_status {
     GSR_E_NOMEM = -3,       /* device allocation failed                                    */
     GSR_E_HIP = -4,         /* a HIP runtime call failed                                   */
     GSR_E_BREAKDOWN = -5,   /* non-finite value met inside the iteration                   */
-    GSR_E_UNSUPPORTED = -6, /* valid request this build does not support                   */
+    GSR_E_UNSUPPORTED = -6, /* valid request the library does not support                  */
     GSR_E_NODEVICE = -7     /* no usable gfx950 device                                     */
 } gsr_status;
 
