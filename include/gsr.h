@@ -95,7 +95,7 @@ typedef struct gsr_solve_opts {
                             btol and conlim tests, Paige & Saunders' three tests at
                             machine precision also stop the iteration (istop 6, 7, 8)    */
     int32_t refine_itnlim; /* GSR_F32V: iteration limit of the correction solves after the
-                            first (0 = itnlim); they only remove a binary32-level error  */
+                            first (0 = itnlim)                                          */
     int32_t reserved;
 } gsr_solve_opts;
 
