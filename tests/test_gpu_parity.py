@@ -417,6 +417,12 @@ def test_stream_ordered_solve_and_graph_capture(cfg_small):
         assert abs(f[key] - ref[key]) <= 1e-10 * abs(ref[key]), key
     with pytest.raises(gsr.GsrError):
         gsr.gsr_lsqr_solve_async(h, cuda(c["b"]), x, info, gsr.solve_opts(profile=True))
+    # zero right-hand side: no step, x = 0, the reason in device memory
+    x.fill_(1.0)
+    gsr.gsr_lsqr_solve_async(h, torch.zeros(S.m, dtype=torch.float64, device="cuda"), x, info,
+                             o)
+    f0 = gsr.read_solve_info(info)
+    assert (f0["itn"], f0["istop"]) == (0, 4) and float(x.abs().max()) == 0.0
 
     bg = cuda(c["b"])
     xg = torch.empty_like(xs)
