@@ -305,8 +305,46 @@ static __global__ void k_final(int64_t n, const double* __restrict__ p, double* 
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int G,
                                                   double* sh) {
     double acc = 0.0;
+#pragma unroll 4
     for (int k = threadIdx.x; k < G; k += kBlock) acc += part[k];
     return block_sum<kBlock>(acc, sh);  // thread 0
+}
+
+// reduce_partials of four arrays at once (p0 of G0 entries; p1, p2, p3 of G1 each): the loads
+// of all four are issued together and one shared-memory exchange serves them; the summation
+// order of each array is that of reduce_partials.  Results valid in thread 0.
+__device__ __forceinline__ void reduce_partials4(const double* __restrict__ p0, int G0,
+                                                 const double* __restrict__ p1,
+                                                 const double* __restrict__ p2,
+                                                 const double* __restrict__ p3, int G1,
+                                                 double (&out)[4],
+                                                 double (&sh)[4][kBlock / kWave]) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = threadIdx.x; k < G0; k += kBlock) a[0] += p0[k];
+#pragma unroll 4
+    for (int k = threadIdx.x; k < G1; k += kBlock) {
+        a[1] += p1[k];
+        a[2] += p2[k];
+        a[3] += p3[k];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = wave_sum(a[q]);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh[q][w] = a[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double r = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBlock / kWave; ++k) r += sh[q][k];
+            out[q] = r;
+        }
+    }
 }
 
 // The scalar recurrences of one LSQR instance (applied by one thread per instance).
@@ -482,13 +520,11 @@ static __global__ __launch_bounds__(kBlock) void k_scal_beta(LsqrState* st, cons
 // pz: partial sums of z_{i-1}^2, z_{i-1} w_i, w_i^2 (rows of Gz).
 static __global__ __launch_bounds__(kBlock) void k_scal_alpha(LsqrState* st, const double* pv,
                                                               int Gv, const double* pz, int Gz) {
-    __shared__ double sh[kBlock / kWave];
+    __shared__ double sh[4][kBlock / kWave];
     if (st->stop) return;
-    const double vv = reduce_partials(pv, Gv, sh);
-    const double zz = reduce_partials(pz, Gz, sh);
-    const double zw = reduce_partials(pz + Gz, Gz, sh);
-    const double ww = reduce_partials(pz + 2 * Gz, Gz, sh);
-    if (threadIdx.x == 0) scal_alpha(st, vv, zz, zw, ww);
+    double r[4];
+    reduce_partials4(pv, Gv, pz, pz + Gz, pz + 2 * Gz, Gz, r, sh);
+    if (threadIdx.x == 0) scal_alpha(st, r[0], r[1], r[2], r[3]);
 }
 
 // ---------------------------------------------------------------------------------------
