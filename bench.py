@@ -661,6 +661,19 @@ def main() -> None:
                 (ab["aprod1"] + ab["aprod2"]) / ((ms1 + ms2) * 1e-3) / 1e9, 1),
         }
 
+    if not args.no_events:
+        # the same solves replayed from the captured iteration graph, without the events the
+        # timed region records around every pass (outside the timed region; context only)
+        gopts = gsr.solve_opts(itnlim=args.iters, fixed_iters=True)
+        gsr.gsr_lsqr_solve(h, b, x, gopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gsr.gsr_lsqr_solve(h, b, x, gopts)
+        torch.cuda.synchronize()
+        extra["iterations_per_s_graph_replay"] = round(
+            args.steps * args.iters / (time.perf_counter() - t0), 3)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(shape, sysd, b.cpu().numpy())
