@@ -41,6 +41,12 @@ class Dims(ctypes.Structure):
                 ("n_glob", ctypes.c_int32)]
 
 
+class Con(ctypes.Structure):
+    """Constraint rows (compressed row form, absolute columns, binary64 values)."""
+    _fields_ = [("n_con", ctypes.c_int64), ("ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("itn", ctypes.c_int32), ("istop", ctypes.c_int32),
                 ("rnorm", ctypes.c_double), ("arnorm", ctypes.c_double),
@@ -62,28 +68,29 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         pd = ctypes.POINTER(Dims)
+        pc = ctypes.c_void_p  # or_con * (NULL: no constraint rows)
         lib.or_n_cols.restype = ctypes.c_int64
         lib.or_n_cols.argtypes = [pd]
         for name in ("or_aprod1", "or_aprod2"):
             f = getattr(lib, name)
             f.restype = None
-            f.argtypes = [pd, vp, vp, vp, vp, vp, vp]
+            f.argtypes = [pd, vp, vp, vp, vp, pc, vp, vp]
         lib.or_colnorm.restype = None
-        lib.or_colnorm.argtypes = [pd, vp, vp, vp, vp, vp]
+        lib.or_colnorm.argtypes = [pd, vp, vp, vp, vp, pc, vp]
         lib.or_pclsqr.restype = ctypes.c_int
-        lib.or_pclsqr.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, f64, vp,
+        lib.or_pclsqr.argtypes = [pd, vp, vp, vp, vp, pc, vp, vp, i32, i32, f64, f64, f64, vp,
                                   ctypes.POINTER(Info), vp]
         lib.or_pclsqr_var.restype = ctypes.c_int
-        lib.or_pclsqr_var.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, f64, vp,
-                                      vp, ctypes.POINTER(Info)]
+        lib.or_pclsqr_var.argtypes = [pd, vp, vp, vp, vp, pc, vp, vp, i32, i32, f64, f64, f64,
+                                      vp, vp, ctypes.POINTER(Info)]
         lib.or_lsqr_transposed.restype = ctypes.c_int
-        lib.or_lsqr_transposed.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, i32, f64, f64, f64,
-                                           vp, ctypes.POINTER(Info)]
+        lib.or_lsqr_transposed.argtypes = [pd, vp, vp, vp, vp, pc, vp, vp, i32, i32, f64, f64,
+                                           f64, vp, ctypes.POINTER(Info)]
         lib.or_residual.restype = None
-        lib.or_residual.argtypes = [pd, vp, vp, vp, vp, vp, vp, vp]
+        lib.or_residual.argtypes = [pd, vp, vp, vp, vp, pc, vp, vp, vp]
         lib.or_refine.restype = i32
-        lib.or_refine.argtypes = [pd, vp, vp, vp, vp, vp, vp, i32, f64, i32, i32, i32, f64, f64,
-                                  vp, vp]
+        lib.or_refine.argtypes = [pd, vp, vp, vp, vp, vp, pc, vp, i32, f64, i32, i32, i32, f64,
+                                  f64, vp, vp]
         lib.or_grad_vals.restype = None
         lib.or_grad_vals.argtypes = [pd, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = lib
@@ -105,13 +112,21 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
 class System:
     """A system in the compressed row format (Section 3): per row 24 coefficients in the
     slot order [5 astrometric | 3x4 attitude | 6 instrumental | 1 global], the star
     number, the attitude start t (relative to the attitude section) and 6 instrumental
-    indices (relative to the instrumental section)."""
+    indices (relative to the instrumental section).
 
-    def __init__(self, dims: dict, vals, star, att, instr):
+    `con` (optional): constraint equations appended below the observation rows, a dict
+    with ``ptr`` [n_con+1] int64, ``col`` [nnz] int64 (absolute columns) and ``val`` [nnz]
+    float64.  Row-space vectors (b, y, r, mu) then have n_rows + n_con entries."""
+
+    def __init__(self, dims: dict, vals, star, att, instr, con: dict | None = None):
         self.d = Dims(int(dims["n_rows"]), int(dims["n_stars"]), int(dims["n_dfa"]),
                       int(dims["n_instr"]), int(dims.get("n_glob", 1)))
         assert self.d.n_glob == 1
@@ -122,10 +137,29 @@ class System:
         m = self.d.n_rows
         assert self.vals.size == 24 * m and self.star.size == m and self.att.size == m
         assert self.instr.size == 6 * m
+        self.con = None
+        self._con = None
+        if con is not None:
+            ptr, col, val = _i64(con["ptr"]), _i64(con["col"]), _f64(con["val"])
+            assert ptr.size >= 1 and ptr[0] == 0 and col.size == val.size == ptr[-1]
+            assert np.all(np.diff(ptr) >= 0)
+            if col.size:
+                assert col.min() >= 0 and col.max() < self.n
+            self.con = dict(ptr=ptr, col=col, val=val)
+            self._con = Con(ptr.size - 1, _p(ptr), _p(col) if col.size else None,
+                            _p(val) if val.size else None)
 
     @property
     def m(self) -> int:
-        return self.d.n_rows
+        """Rows of the operator: observation rows plus constraint rows."""
+        return self.d.n_rows + self.n_con
+
+    @property
+    def n_con(self) -> int:
+        return 0 if self._con is None else int(self._con.n_con)
+
+    def _cp(self):
+        return None if self._con is None else ctypes.addressof(self._con)
 
     @property
     def n(self) -> int:
@@ -133,12 +167,12 @@ class System:
 
     def _args(self, vals=None):
         return (ctypes.byref(self.d), _p(self.vals if vals is None else vals), _p(self.star),
-                _p(self.att), _p(self.instr))
+                _p(self.att), _p(self.instr), self._cp())
 
     def with_vals(self, vals) -> "System":
         return System(dict(n_rows=self.d.n_rows, n_stars=self.d.n_stars, n_dfa=self.d.n_dfa,
                            n_instr=self.d.n_instr, n_glob=1), vals, self.star, self.att,
-                      self.instr)
+                      self.instr, con=self.con)
 
     # Algorithm 1
     def aprod1(self, x, y=None) -> np.ndarray:
@@ -225,7 +259,7 @@ class System:
         x = np.empty(self.n)
         inner = np.zeros(max(max_outer, 1), dtype=np.int32)
         k = _load().or_refine(ctypes.byref(self.d), _p(self.vals), _p(lo), _p(self.star),
-                              _p(self.att), _p(self.instr), _p(b), int(max_outer),
+                              _p(self.att), _p(self.instr), self._cp(), _p(b), int(max_outer),
                               float(refine_tol), int(inner_itnlim), int(later_itnlim),
                               int(bool(inner_fixed)),
                               float(inner_atol), float(inner_btol), _p(x), _p(inner))
@@ -233,7 +267,7 @@ class System:
 
     def grad_vals(self, r, mu, x, lam) -> np.ndarray:
         r, mu, x, lam = _f64(r), _f64(mu), _f64(x), _f64(lam)
-        dv = np.empty(24 * self.m)
+        dv = np.empty(24 * self.d.n_rows)
         _load().or_grad_vals(ctypes.byref(self.d), _p(self.star), _p(self.att), _p(self.instr),
                              _p(r), _p(mu), _p(x), _p(lam), _p(dv))
         return dv

@@ -32,7 +32,14 @@
  *   - the variances the paper updates every iteration (Section 3, flowchart
  *     paragraph) are Paige & Saunders' estimate of diag((A^T A)^-1): the sum over
  *     the iterations of (w_i / rho_i)^2 in the preconditioned unknowns, multiplied
- *     by p^2 at the end like the solution is multiplied by p.
+ *     by p^2 at the end like the solution is multiplied by p;
+ *   - the constraint equations (Section 3: extra equations that make the
+ *     solution unique; Algorithms 1 and 2 end with a "constraints
+ *     computation" region after the observation rows) are sparse rows C,
+ *     given by the caller, appended below the observation rows: the system
+ *     becomes [A; C] x ~ [b; c].  aprod 1 writes their entries after the n_rows
+ *     observation entries of y, aprod 2 adds C^T y_c after the observation part,
+ *     and the column norms of the preconditioner include them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -61,6 +68,18 @@ typedef struct {
                         sqrt(sum ||w_i / rho_i||^2)                           */
 } or_info;
 
+/* Constraint equations: n_con sparse rows in compressed row form; row k holds
+ * val[ptr[k] .. ptr[k+1]-1] at the absolute columns col[...] (repeated columns
+ * add up).  A NULL or_con means no constraint rows. */
+typedef struct {
+    int64_t n_con;
+    const int64_t *ptr;
+    const int64_t *col;
+    const double *val;
+} or_con;
+
+static int64_t con_rows(const or_con *con) { return con ? con->n_con : 0; }
+
 /* Number of unknowns: astrometric, attitude, instrumental and global sections. */
 int64_t or_n_cols(const or_dims *d)
 {
@@ -88,9 +107,10 @@ static int64_t col_of(const or_dims *d, const int32_t *star, const int32_t *att,
 }
 
 /* aprod 1 (Algorithm 1): y[i] += sum_k A_d[i,k] x[col(i,k)], rows in order,
- * coefficients in slot order. */
+ * coefficients in slot order; then the constraint rows ("constraints
+ * computation"): y[n_rows + k] += sum_e val[e] x[col[e]]. */
 void or_aprod1(const or_dims *d, const double *vals, const int32_t *star, const int32_t *att,
-               const int32_t *instr, const double *x, double *y)
+               const int32_t *instr, const or_con *con, const double *x, double *y)
 {
     for (int64_t i = 0; i < d->n_rows; ++i) {
         double sum = 0.0;
@@ -98,21 +118,31 @@ void or_aprod1(const or_dims *d, const double *vals, const int32_t *star, const 
             sum += vals[24 * i + k] * x[col_of(d, star, att, instr, i, k)];
         y[i] += sum;
     }
+    for (int64_t k = 0; k < con_rows(con); ++k) {
+        double sum = 0.0;
+        for (int64_t e = con->ptr[k]; e < con->ptr[k + 1]; ++e)
+            sum += con->val[e] * x[con->col[e]];
+        y[d->n_rows + k] += sum;
+    }
 }
 
-/* aprod 2 (Algorithm 2): x[col(i,k)] += A_d[i,k] * y[i], rows in order. */
+/* aprod 2 (Algorithm 2): x[col(i,k)] += A_d[i,k] * y[i], rows in order; then the
+ * constraint rows: x[col[e]] += val[e] * y[n_rows + k]. */
 void or_aprod2(const or_dims *d, const double *vals, const int32_t *star, const int32_t *att,
-               const int32_t *instr, const double *y, double *x)
+               const int32_t *instr, const or_con *con, const double *y, double *x)
 {
     for (int64_t i = 0; i < d->n_rows; ++i)
         for (int k = 0; k < 24; ++k)
             x[col_of(d, star, att, instr, i, k)] += vals[24 * i + k] * y[i];
+    for (int64_t k = 0; k < con_rows(con); ++k)
+        for (int64_t e = con->ptr[k]; e < con->ptr[k + 1]; ++e)
+            x[con->col[e]] += con->val[e] * y[d->n_rows + k];
 }
 
 /* Column-norm preconditioner (Section 2, PC-LSQR paragraph):
- * p[j] = 1 / ||A e_j||_2, or 0 for an all-zero column. */
+ * p[j] = 1 / ||[A; C] e_j||_2, or 0 for an all-zero column. */
 void or_colnorm(const or_dims *d, const double *vals, const int32_t *star, const int32_t *att,
-                const int32_t *instr, double *p)
+                const int32_t *instr, const or_con *con, double *p)
 {
     const int64_t n = or_n_cols(d);
     double *ss = calloc((size_t)n, sizeof(double));
@@ -121,6 +151,9 @@ void or_colnorm(const or_dims *d, const double *vals, const int32_t *star, const
             const double a = vals[24 * i + k];
             ss[col_of(d, star, att, instr, i, k)] += a * a;
         }
+    for (int64_t k = 0; k < con_rows(con); ++k)
+        for (int64_t e = con->ptr[k]; e < con->ptr[k + 1]; ++e)
+            ss[con->col[e]] += con->val[e] * con->val[e];
     for (int64_t j = 0; j < n; ++j)
         p[j] = ss[j] > 0.0 ? 1.0 / sqrt(ss[j]) : 0.0;
     free(ss);
@@ -135,13 +168,15 @@ typedef struct {
     const or_dims *d;
     const double *vals;
     const int32_t *star, *att, *instr;
+    const or_con *con; /* constraint rows below A (NULL: none) */
     const double *p;
     int transpose;
     double *tmp; /* n_cols scratch */
 } or_op;
 
-static int64_t op_rows(const or_op *op) { return op->transpose ? or_n_cols(op->d) : op->d->n_rows; }
-static int64_t op_cols(const or_op *op) { return op->transpose ? op->d->n_rows : or_n_cols(op->d); }
+static int64_t all_rows(const or_op *op) { return op->d->n_rows + con_rows(op->con); }
+static int64_t op_rows(const or_op *op) { return op->transpose ? or_n_cols(op->d) : all_rows(op); }
+static int64_t op_cols(const or_op *op) { return op->transpose ? all_rows(op) : or_n_cols(op->d); }
 
 /* y += A (p o x) */
 static void apply_AD(const or_op *op, const double *x, double *y)
@@ -149,7 +184,7 @@ static void apply_AD(const or_op *op, const double *x, double *y)
     const int64_t n = or_n_cols(op->d);
     for (int64_t j = 0; j < n; ++j)
         op->tmp[j] = op->p ? op->p[j] * x[j] : x[j];
-    or_aprod1(op->d, op->vals, op->star, op->att, op->instr, op->tmp, y);
+    or_aprod1(op->d, op->vals, op->star, op->att, op->instr, op->con, op->tmp, y);
 }
 
 /* x += p o (A^T y) */
@@ -157,7 +192,7 @@ static void apply_DAt(const or_op *op, const double *y, double *x)
 {
     const int64_t n = or_n_cols(op->d);
     memset(op->tmp, 0, (size_t)n * sizeof(double));
-    or_aprod2(op->d, op->vals, op->star, op->att, op->instr, y, op->tmp);
+    or_aprod2(op->d, op->vals, op->star, op->att, op->instr, op->con, y, op->tmp);
     for (int64_t j = 0; j < n; ++j)
         x[j] += op->p ? op->p[j] * op->tmp[j] : op->tmp[j];
 }
@@ -347,12 +382,13 @@ done:
  * solution is re-multiplied by p at the end (Section 3, flowchart paragraph).
  */
 int or_pclsqr(const or_dims *d, const double *vals, const int32_t *star, const int32_t *att,
-              const int32_t *instr, const double *p, const double *b, int32_t itnlim,
+              const int32_t *instr, const or_con *con, const double *p, const double *b,
+              int32_t itnlim,
               int32_t fixed, double atol, double btol, double conlim, double *x,
               or_info *info, double *hist_rnorm)
 {
     const int64_t n = or_n_cols(d);
-    or_op op = {d, vals, star, att, instr, p, 0, malloc((size_t)n * sizeof(double))};
+    or_op op = {d, vals, star, att, instr, con, p, 0, malloc((size_t)n * sizeof(double))};
     const int rc =
         lsqr_core(&op, b, itnlim, fixed, atol, btol, conlim, x, info, hist_rnorm, NULL);
     if (p)
@@ -368,12 +404,13 @@ int or_pclsqr(const or_dims *d, const double *vals, const int32_t *star, const i
  * under independent residuals is sqrt(var[j]) * ||r|| / sqrt(n_rows - n_cols).
  */
 int or_pclsqr_var(const or_dims *d, const double *vals, const int32_t *star,
-                  const int32_t *att, const int32_t *instr, const double *p, const double *b,
+                  const int32_t *att, const int32_t *instr, const or_con *con, const double *p,
+                  const double *b,
                   int32_t itnlim, int32_t fixed, double atol, double btol, double conlim,
                   double *x, double *var, or_info *info)
 {
     const int64_t n = or_n_cols(d);
-    or_op op = {d, vals, star, att, instr, p, 0, malloc((size_t)n * sizeof(double))};
+    or_op op = {d, vals, star, att, instr, con, p, 0, malloc((size_t)n * sizeof(double))};
     const int rc = lsqr_core(&op, b, itnlim, fixed, atol, btol, conlim, x, info, NULL, var);
     if (p)
         for (int64_t j = 0; j < n; ++j) {
@@ -385,12 +422,13 @@ int or_pclsqr_var(const or_dims *d, const double *vals, const int32_t *star,
 }
 
 /*
- * Minimum-norm solution mu (length n_rows) of A^T mu = g: LSQR from zero on the
- * transposed, row-scaled system D A^T mu = D g (same solution set when p has no
- * zeros).  Used by the adjoint of the least-squares solve.
+ * Minimum-norm solution mu (length n_rows + n_con) of A^T mu = g (A with its constraint
+ * rows): LSQR from zero on the transposed, row-scaled system D A^T mu = D g (same solution
+ * set when p has no zeros).  Used by the adjoint of the least-squares solve.
  */
 int or_lsqr_transposed(const or_dims *d, const double *vals, const int32_t *star,
-                       const int32_t *att, const int32_t *instr, const double *p, const double *g,
+                       const int32_t *att, const int32_t *instr, const or_con *con,
+                       const double *p, const double *g,
                        int32_t itnlim, int32_t fixed, double atol, double btol, double conlim,
                        double *mu, or_info *info)
 {
@@ -398,28 +436,30 @@ int or_lsqr_transposed(const or_dims *d, const double *vals, const int32_t *star
     double *rhs = malloc((size_t)n * sizeof(double));
     for (int64_t j = 0; j < n; ++j)
         rhs[j] = p ? p[j] * g[j] : g[j];
-    or_op op = {d, vals, star, att, instr, p, 1, malloc((size_t)n * sizeof(double))};
+    or_op op = {d, vals, star, att, instr, con, p, 1, malloc((size_t)n * sizeof(double))};
     const int rc = lsqr_core(&op, rhs, itnlim, fixed, atol, btol, conlim, mu, info, NULL, NULL);
     free(op.tmp);
     free(rhs);
     return rc;
 }
 
-/* r = b - A x */
+/* r = b - A x (over the observation and the constraint rows) */
 void or_residual(const or_dims *d, const double *vals, const int32_t *star, const int32_t *att,
-                 const int32_t *instr, const double *b, const double *x, double *r)
+                 const int32_t *instr, const or_con *con, const double *b, const double *x,
+                 double *r)
 {
-    const int64_t m = d->n_rows;
+    const int64_t m = d->n_rows + con_rows(con);
     for (int64_t i = 0; i < m; ++i)
         r[i] = 0.0;
-    or_aprod1(d, vals, star, att, instr, x, r);
+    or_aprod1(d, vals, star, att, instr, con, x, r);
     for (int64_t i = 0; i < m; ++i)
         r[i] = b[i] - r[i];
 }
 
 /*
  * Mixed-precision form: vals_lo holds the same coefficients rounded to binary32 and
- * widened back (exactly) to double.  Residual correction:
+ * widened back (exactly) to double (constraint rows, if any, stay binary64 on both
+ * sides).  Residual correction:
  *   x_0 = 0, r_0 = b;  for k = 0, 1, ...:  d_k = PC-LSQR(A_lo, r_k) with p_lo from A_lo,
  *   x_{k+1} = x_k + d_k; stop when ||d_k|| <= refine_tol ||x_{k+1}||;
  *   otherwise r_{k+1} = b - A x_{k+1} with the double-precision coefficients.
@@ -429,15 +469,15 @@ void or_residual(const or_dims *d, const double *vals, const int32_t *star, cons
  */
 int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
                   const int32_t *star, const int32_t *att, const int32_t *instr,
-                  const double *b, int32_t max_outer, double refine_tol, int32_t inner_itnlim,
-                  int32_t later_itnlim, int32_t inner_fixed, double inner_atol,
+                  const or_con *con, const double *b, int32_t max_outer, double refine_tol,
+                  int32_t inner_itnlim, int32_t later_itnlim, int32_t inner_fixed, double inner_atol,
                   double inner_btol, double *x, int32_t *inner_itn)
 {
-    const int64_t m = d->n_rows, n = or_n_cols(d);
+    const int64_t m = d->n_rows + con_rows(con), n = or_n_cols(d);
     double *p_lo = malloc((size_t)n * sizeof(double));
     double *r = malloc((size_t)m * sizeof(double));
     double *dx = malloc((size_t)n * sizeof(double));
-    or_colnorm(d, vals_lo, star, att, instr, p_lo);
+    or_colnorm(d, vals_lo, star, att, instr, con, p_lo);
     memcpy(r, b, (size_t)m * sizeof(double));
     memset(x, 0, (size_t)n * sizeof(double));
     int32_t k = 0;
@@ -445,7 +485,7 @@ int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
         or_info info;
         /* the correction solves after the first may take a shorter iteration limit */
         const int32_t itnlim = (k > 0 && later_itnlim > 0) ? later_itnlim : inner_itnlim;
-        or_pclsqr(d, vals_lo, star, att, instr, p_lo, r, itnlim, inner_fixed, inner_atol,
+        or_pclsqr(d, vals_lo, star, att, instr, con, p_lo, r, itnlim, inner_fixed, inner_atol,
                   inner_btol, 0.0, dx, &info, NULL);
         if (inner_itn)
             inner_itn[k] = info.itn;
@@ -454,7 +494,7 @@ int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
         ++k;
         if (nrm2(dx, n) <= refine_tol * nrm2(x, n))
             break;
-        or_residual(d, vals, star, att, instr, b, x, r);
+        or_residual(d, vals, star, att, instr, con, b, x, r);
     }
     free(p_lo);
     free(r);

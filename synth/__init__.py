@@ -32,6 +32,7 @@ STREAM_XTRUE = 4
 STREAM_NOISE = 5
 STREAM_XREF = 7
 STREAM_STARS = 8
+STREAM_CON_VALS = 10
 STREAM_RHS_X = 64
 STREAM_RHS_NOISE = 4096
 
@@ -72,6 +73,8 @@ def _load():
         lib.syn_star_counts.argtypes = [u64, i64, i32, i32, vp]
         lib.syn_rows.restype = None
         lib.syn_rows.argtypes = [u64, i32, i32, i64, i64, vp, vp, vp]
+        lib.syn_primary_stars.restype = i64
+        lib.syn_primary_stars.argtypes = [u64, i64, ctypes.c_double, vp]
         lib.syn_star_of_rows.restype = None
         lib.syn_star_of_rows.argtypes = [vp, i64, i64, i64, vp]
         _lib = lib
@@ -196,6 +199,35 @@ def rhs_x(shape: Shape, j: int) -> np.ndarray:
 def rhs_noise(shape: Shape, j: int, n_rows: int | None = None) -> np.ndarray:
     m = shape.n_rows if n_rows is None else n_rows
     return normals(shape.seed, STREAM_RHS_NOISE + j, m, SIGMA_NOISE)
+
+
+def primary_stars(shape: Shape, frac: float) -> np.ndarray:
+    """Stars selected (each with probability `frac`) for the constraint rows."""
+    lib = _load()
+    n = int(lib.syn_primary_stars(shape.seed, shape.n_stars, float(frac), None))
+    out = np.empty(n, dtype=np.int32)
+    if n:
+        lib.syn_primary_stars(shape.seed, shape.n_stars, float(frac), _ptr(out))
+    return out
+
+
+def frame_constraints(shape: Shape, n_con: int = 6, frac: float = 0.1) -> dict:
+    """Constraint rows shaped like the reference-frame conditions of a global astrometric
+    solution: every row touches two astrometric unknowns of each selected ("primary") star
+    -- slots 1, 2 (position-like) in the first half of the rows, slots 3, 4 (motion-like)
+    in the second half -- with N(0, 1) coefficients.  Returns ptr [n_con+1] int64, col
+    [nnz] int64 (absolute columns, ascending within a row), val [nnz] float64."""
+    prim = primary_stars(shape, frac).astype(np.int64)
+    per = 2 * prim.size
+    ptr = np.arange(n_con + 1, dtype=np.int64) * per
+    col = np.empty(n_con * per, dtype=np.int64)
+    for k in range(n_con):
+        a = 1 if k < (n_con + 1) // 2 else 3
+        blk = col[k * per:(k + 1) * per].reshape(-1, 2)
+        blk[:, 0] = 5 * prim + a
+        blk[:, 1] = 5 * prim + a + 1
+    val = normals(shape.seed, STREAM_CON_VALS, n_con * per)
+    return dict(ptr=ptr, col=col, val=val)
 
 
 # --- the workloads -----------------------------------------------------------------------

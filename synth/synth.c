@@ -40,6 +40,8 @@ enum {
     SYN_STREAM_OBS = 6,
     SYN_STREAM_XREF = 7,
     SYN_STREAM_STARS = 8,
+    SYN_STREAM_PRIMARY = 9,     /* selection of the stars the constraint rows touch */
+    SYN_STREAM_CON_VALS = 10,   /* coefficients of the constraint rows              */
     SYN_STREAM_RHS_X = 64,      /* + j for right-hand side j   */
     SYN_STREAM_RHS_NOISE = 4096 /* + j for right-hand side j   */
 };
@@ -182,4 +184,20 @@ void syn_star_of_rows(const int64_t *row_ptr, int64_t n_stars, int64_t row_begin
             ++s;
         star[r - row_begin] = (int32_t)s;
     }
+}
+
+/* Stars selected for the constraint rows: star s is selected when
+ * uniform(PRIMARY, s) < frac.  Writes the selected star numbers (ascending) to
+ * `out` when it is not NULL; returns how many there are. */
+int64_t syn_primary_stars(uint64_t seed, int64_t n_stars, double frac, int32_t *out)
+{
+    const uint64_t key = syn_key(seed, SYN_STREAM_PRIMARY);
+    int64_t n = 0;
+    for (int64_t s = 0; s < n_stars; ++s)
+        if (syn_uniform(key, (uint64_t)s) < frac) {
+            if (out)
+                out[n] = (int32_t)s;
+            ++n;
+        }
+    return n;
 }
