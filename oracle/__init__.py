@@ -90,7 +90,7 @@ def _load():
         lib.or_residual.argtypes = [pd, vp, vp, vp, vp, pc, vp, vp, vp]
         lib.or_refine.restype = i32
         lib.or_refine.argtypes = [pd, vp, vp, vp, vp, vp, pc, vp, i32, f64, i32, i32, i32, f64,
-                                  f64, vp, vp]
+                                  f64, f64, vp, vp]
         lib.or_grad_vals.restype = None
         lib.or_grad_vals.argtypes = [pd, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = lib
@@ -249,11 +249,12 @@ class System:
         return r
 
     def refine(self, b, vals_lo, max_outer=5, refine_tol=1e-10, inner_itnlim=200,
-               inner_fixed=False, inner_atol=1e-14, inner_btol=1e-14, later_itnlim=0):
+               inner_fixed=False, inner_atol=1e-14, inner_btol=1e-14, later_itnlim=0,
+               first_tol=0.0):
         """Mixed-precision residual correction; vals_lo = binary32-rounded coefficients
         (any float array; widened exactly to double); the correction solves after the first
-        take later_itnlim iterations at most (0: inner_itnlim).  Returns (x, outer,
-        inner_itns)."""
+        take later_itnlim iterations at most (0: inner_itnlim); the first inner solve stops
+        at atol = btol = first_tol when first_tol > 0.  Returns (x, outer, inner_itns)."""
         b = _f64(b)
         lo = np.ascontiguousarray(np.asarray(vals_lo, dtype=np.float32).astype(np.float64))
         x = np.empty(self.n)
@@ -262,7 +263,8 @@ class System:
                               _p(self.att), _p(self.instr), self._cp(), _p(b), int(max_outer),
                               float(refine_tol), int(inner_itnlim), int(later_itnlim),
                               int(bool(inner_fixed)),
-                              float(inner_atol), float(inner_btol), _p(x), _p(inner))
+                              float(inner_atol), float(inner_btol), float(first_tol), _p(x),
+                              _p(inner))
         return x, int(k), inner[:k].tolist()
 
     def grad_vals(self, r, mu, x, lam) -> np.ndarray:

@@ -464,14 +464,16 @@ void or_residual(const or_dims *d, const double *vals, const int32_t *star, cons
  *   x_{k+1} = x_k + d_k; stop when ||d_k|| <= refine_tol ||x_{k+1}||;
  *   otherwise r_{k+1} = b - A x_{k+1} with the double-precision coefficients.
  * The first inner solve takes at most inner_itnlim iterations, the later ones (which only
- * correct an error at the binary32 level) at most later_itnlim (0: inner_itnlim).
+ * correct an error at the binary32 level) at most later_itnlim (0: inner_itnlim).  With
+ * first_tol > 0 the first inner solve stops on the Paige & Saunders tests at
+ * atol = btol = first_tol, the later ones at inner_atol, inner_btol.
  * Returns the number of outer steps; inner iteration counts go to inner_itn[k].
  */
 int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
                   const int32_t *star, const int32_t *att, const int32_t *instr,
                   const or_con *con, const double *b, int32_t max_outer, double refine_tol,
                   int32_t inner_itnlim, int32_t later_itnlim, int32_t inner_fixed, double inner_atol,
-                  double inner_btol, double *x, int32_t *inner_itn)
+                  double inner_btol, double first_tol, double *x, int32_t *inner_itn)
 {
     const int64_t m = d->n_rows + con_rows(con), n = or_n_cols(d);
     double *p_lo = malloc((size_t)n * sizeof(double));
@@ -485,8 +487,12 @@ int32_t or_refine(const or_dims *d, const double *vals, const double *vals_lo,
         or_info info;
         /* the correction solves after the first may take a shorter iteration limit */
         const int32_t itnlim = (k > 0 && later_itnlim > 0) ? later_itnlim : inner_itnlim;
-        or_pclsqr(d, vals_lo, star, att, instr, con, p_lo, r, itnlim, inner_fixed, inner_atol,
-                  inner_btol, 0.0, dx, &info, NULL);
+        /* ... and the first one its own (looser) tolerance: its result cannot be closer to
+         * the binary64 solution than the binary32 rounding of the coefficients allows */
+        const double ta = (k == 0 && first_tol > 0.0) ? first_tol : inner_atol;
+        const double tb = (k == 0 && first_tol > 0.0) ? first_tol : inner_btol;
+        or_pclsqr(d, vals_lo, star, att, instr, con, p_lo, r, itnlim, inner_fixed, ta, tb, 0.0,
+                  dx, &info, NULL);
         if (inner_itn)
             inner_itn[k] = info.itn;
         for (int64_t j = 0; j < n; ++j)

@@ -364,6 +364,27 @@ def test_refine_schedule_with_short_correction_solves():
     assert np.linalg.norm(xr - x64) <= 1e-9 * np.linalg.norm(x64)
 
 
+def test_refine_with_loose_first_solve():
+    """A first inner solve stopped at a loose tolerance, then correction solves at the final
+    one: the composition written out with scipy's sparse residual, and the binary64 solution
+    reached."""
+    shape = synth.S1K_O60
+    s, S = _system(shape)
+    A = csr(s["dims"], s["vals"], s["star"], s["att"], s["instr"])
+    b = A @ synth.x_true(shape) + synth.noise(shape)
+    lo = s["vals"].astype(np.float32)
+    S32 = S.with_vals(lo.astype(np.float64))
+    x1, i1 = S32.lsqr(b, itnlim=300, fixed=False, atol=1e-4, btol=1e-4)
+    d1, i2 = S32.lsqr(b - A @ x1, itnlim=300, fixed=False, atol=1e-12, btol=1e-12)
+    xr, outer, inner = S.refine(b, lo, max_outer=2, refine_tol=0.0, inner_itnlim=300,
+                                inner_atol=1e-12, inner_btol=1e-12, first_tol=1e-4)
+    assert (outer, inner) == (2, [i1["itn"], i2["itn"]])
+    assert i1["itn"] < i2["itn"]
+    assert np.linalg.norm(xr - (x1 + d1)) <= 1e-13 * np.linalg.norm(xr)
+    x64, _ = S.lsqr(b, itnlim=300, fixed=False, atol=1e-15, btol=1e-15)
+    assert np.linalg.norm(xr - x64) <= 1e-9 * np.linalg.norm(x64)
+
+
 def test_refine_with_exact_low_precision_is_one_solve():
     shape = synth.Shape(10, 20, 20, 10, 12, seed=15)
     s, S = _system(shape)
