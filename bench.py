@@ -1,14 +1,17 @@
 """Benchmark of the PC-LSQR hot path on one MI355X.
 
-Default workload: the 2e7-row system (1e6 stars x 20 observations, N_DFA 30,000, 6,000
-instrumental columns), plain binary64 PC-LSQR with the column-norm preconditioner, 200
-iterations per step.  A step is one whole solve (initial aprod 2, 200 iterations of
-aprod 1 / aprod 2 / Givens / vector updates, final scaling) on inputs resident in HBM; the
-preconditioner is computed once at setup and timed separately.
+Default workload: the 2e8-row system (5e6 stars x 40 observations, N_DFA 100,000, 10,000
+instrumental columns, 25,310,001 unknowns), inputs generated on the host and resident in HBM
+before anything is timed.  A step is one binary64 PC-LSQR solve of 100 fixed iterations
+(initial aprod 2, then per iteration aprod 1 / aprod 2 / Givens / vector updates, final
+scaling); the preconditioner is computed once at setup and timed separately.
 
-Prints ONE JSON line: iterations/s over the timed steps, the roofline of the dominant
-product (algorithmic bytes / mean launch duration, HIP events inside the timed region) and
-the CPU oracle timed on a bounded sample of the same workload.
+Prints ONE JSON line: binary64 iterations/s over the timed steps, the roofline of the
+dominant pass (algorithmic bytes / mean launch duration, HIP events inside the timed
+region) and of the other pass, the precision form against binary64 (time to a 1e-8
+relative solution error, with tolerances fixed before the run and with the best fixed
+schedule found afterwards), and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -49,14 +52,26 @@ def pass_bytes(m: int, n: int, shape, fused: bool, value_bytes: int = 8) -> dict
     return {"pass1": p1, "pass2": p2}
 
 
-def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
-    """The oracle (single-threaded C) on the same system: per-iteration time from the
-    difference of two fixed-iteration solves (setup of p excluded)."""
+def cpu_baseline(shape, b_sample, n_stars_sample: int, iters_lo=1, iters_hi=4) -> dict:
+    """The oracle (single-threaded C) on a bounded sample of the workload: the rows of its
+    first `n_stars_sample` stars (star-aligned, so the sample is itself a system of the same
+    generator with the full attitude and instrumental widths).  Per-iteration time from the
+    difference of two fixed-iteration solves (setup of p excluded); the whole-system rate is
+    the sample's rate scaled by the row ratio (the products, linear in the rows, dominate an
+    iteration)."""
     import numpy as np
 
     import oracle
+    import synth
 
-    S = oracle.System(sysd["dims"], sysd["vals"], sysd["star"], sysd["att"], sysd["instr"])
+    rp = shape.row_ptr()
+    m_s = int(rp[n_stars_sample])
+    t0 = time.perf_counter()
+    part = synth.rows(shape, 0, m_s, row_ptr=rp)
+    t_gen = time.perf_counter() - t0
+    dims = dict(n_rows=m_s, n_stars=n_stars_sample, n_dfa=shape.n_dfa, n_instr=shape.n_instr)
+    S = oracle.System(dims, part["vals"], part["star"], part["att"], part["instr"])
+    b = np.ascontiguousarray(b_sample[:m_s], dtype=np.float64)
     p = S.colnorm()
     t0 = time.perf_counter()
     S.lsqr(b, itnlim=iters_lo, fixed=True, p=p)
@@ -71,11 +86,17 @@ def cpu_baseline(shape, sysd, b, iters_lo=1, iters_hi=4) -> dict:
     t4 = time.perf_counter()
     S.aprod2(b)
     t5 = time.perf_counter()
-    return {"value": 1.0 / per_it, "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters_hi - iters_lo} PC-LSQR iterations of the same {S.m}-row system "
-                      f"(difference of {iters_hi}- and {iters_lo}-iteration solves, "
-                      f"{t2 - t0:.1f} s of CPU work)",
-            "aprod1_s": round(t4 - t3, 4), "aprod2_s": round(t5 - t4, 4),
+    m = shape.n_rows
+    return {"value": (1.0 / per_it) * (m_s / m), "unit": "iterations/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"rows of the first {n_stars_sample} stars ({m_s} of {m} rows, "
+                      f"{S.n} unknowns, full attitude and instrumental widths): "
+                      f"{iters_hi - iters_lo} PC-LSQR iterations from the difference of "
+                      f"{iters_hi}- and {iters_lo}-iteration solves ({t2 - t0:.1f} s of CPU "
+                      f"work), scaled to the whole system by the row ratio",
+            "sample_iterations_per_s": round(1.0 / per_it, 4),
+            "sample_aprod1_s": round(t4 - t3, 4), "sample_aprod2_s": round(t5 - t4, 4),
+            "sample_generation_s": round(t_gen, 2),
             "cpu_model": cpu_model(), "host_cores": os.cpu_count()}
 
 
@@ -156,35 +177,42 @@ def _pmc_means(d: str, counter: str) -> dict:
     by: dict = {}
     for _, name, v in rows:
         by.setdefault(name, []).append(v)
-    out = {k: sum(v) / len(v) for k, v in by.items()}
+    out = {k: (sum(v) / len(v), len(v)) for k, v in by.items()}
     cal = [v for _, name, v in rows if name.startswith("__amd_rocclr_copyBuffer")][:3]
     if len(cal) == 3:
-        out["copy"] = sum(cal) / 3
+        out["copy"] = (sum(cal) / 3, 3)
     return out
 
 
 def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, cmd: str) -> str:
-    """Write the traffic summary of `kernel` (name prefix) from the two counter runs."""
+    """Write the traffic summary of `kernel` from the two counter runs.  `kernel` is the
+    name with its template arguments (e.g. "k_aprod12<double, 1, false, false>", the
+    iteration's fused pass, not the solve's initial variant); the summary file is named by
+    the name before the template arguments."""
     fetch, write = _pmc_means(fetch_dir, "FETCH_SIZE"), _pmc_means(write_dir, "WRITE_SIZE")
 
-    def pick(tab, prefix):
-        keys = [k for k in tab if k.startswith(prefix)]
-        if not keys:
-            raise SystemExit(f"no dispatches of {prefix} in the counter output")
+    def pick(tab, name):
+        keys = [k for k in tab if k == name]
+        if len(keys) != 1:
+            raise SystemExit(f"{len(keys)} kernels named {name} in the counter output")
         return tab[keys[0]], keys[0]
 
-    cf, _ = pick(fetch, "copy")
-    cw, _ = pick(write, "copy")
-    kf, full = pick(fetch, "gsr::" + kernel)
-    kw, _ = pick(write, "gsr::" + kernel)
+    (cf, _), _ = pick(fetch, "copy")
+    (cw, _), _ = pick(write, "copy")
+    (kf, nf), full = pick(fetch, "gsr::" + kernel)
+    (kw, nw), _ = pick(write, "gsr::" + kernel)
     sf, sw = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
     fb, wb = kf * 1024 * sf, kw * 1024 * sw
+    short = kernel.split("<")[0]
     lines = [
         f"# HBM traffic of {full}, workload {workload}",
         f"# commands (FETCH_SIZE, then WRITE_SIZE): {cmd}",
         "# counters are KiB per dispatch (mean over the run's dispatches); each is scaled by the",
         "# ratio of the true 1 GiB read (written) by the calibration copy to what the counter read",
-        f"kernel: {kernel}",
+        f"kernel: {short}",
+        f"kernel_full: {full}",
+        f"dispatches_fetch: {nf}",
+        f"dispatches_write: {nw}",
         f"workload: {workload}",
         f"source_hash: {kernel_source_hash()}",
         f"copy_fetch_kib: {cf:.1f}",
@@ -197,7 +225,7 @@ def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, cmd:
         f"write_bytes_per_launch: {wb:.0f}",
         f"traffic_bytes_per_launch: {fb + wb:.0f}",
     ]
-    out = traffic_path(kernel, workload)
+    out = traffic_path(short, workload)
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     return out
@@ -252,97 +280,123 @@ def upload_system(shape, chunk_rows: int = 10_000_000):
     return t, dims
 
 
-def form_precision(args) -> dict:
+# Tolerances of the precision comparison, fixed before any run: the final tolerance is the
+# 1e-8 target / 100 for both forms; the first binary32 inner solve stops at 1e-6 (about 16
+# binary32 unit roundoffs: its result cannot come closer to the binary64 solution than the
+# rounding of the coefficients allows); a correction step ends the loop once it changes x by
+# less than the target / 10.
+TARGET_REL_ERR = 1e-8
+APRIORI = {"atol": 1e-10, "btol": 1e-10, "refine_first_tol": 1e-6, "refine_tol": 1e-9,
+           "max_refine": 4, "itnlim": 2000}
+
+
+def precision_compare(h, b, shape, m: int, n: int) -> dict:
     """binary64 PC-LSQR vs binary32-coefficient PC-LSQR with binary64 residual correction,
-    both taken to 1e-8 relative error against a converged binary64 reference."""
+    both to TARGET_REL_ERR relative error against a converged binary64 reference:
+    (1) with the tolerances of APRIORI, fixed before the run; (2) with the fewest fixed
+    iterations (binary64) and the best (first, later) inner iteration counts (precision
+    form) found by searching against the reference -- a bound a user cannot set in advance."""
     import torch
 
-    import synth
     from paper_2212_11675_amd import gsr
 
-    shape = synth.WORKLOADS[args.workload]
-    t, d = upload_system(shape)
-    m, n = d["n_rows"], shape.n_cols
-    dev = torch.device("cuda:0")
-    h = gsr.gsr_lsqr_setup(gsr.make_dims(m, d["n_stars"], d["n_dfa"], d["n_instr"]), t["vals"],
-                           t["star"], t["att"], t["instr"], build_f32=True)
-    b = torch.from_numpy(synth.noise(shape)).to(dev)
-    gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
-    x_ref = torch.empty(n, dtype=torch.float64, device=dev)
-    ref = gsr.gsr_lsqr_solve(h, b, x_ref, gsr.solve_opts(itnlim=1000, fixed_iters=False,
+    x_ref = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    ref = gsr.gsr_lsqr_solve(h, b, x_ref, gsr.solve_opts(itnlim=2000, fixed_iters=False,
                                                          atol=1e-15, btol=1e-15))
-    log(f"reference: {ref['itn']} iterations, istop {ref['istop']}")
+    log(f"precision: reference {ref['itn']} iterations, istop {ref['istop']}")
     nref = torch.linalg.norm(x_ref)
     x = torch.empty_like(x_ref)
 
-    def timed(opts):
+    def run(opts):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = gsr.gsr_lsqr_solve(h, b, x, opts)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, info, float(torch.linalg.norm(x - x_ref) / nref)
 
-    # binary64: fewest fixed iterations that reach 1e-8
-    k64, best64 = None, None
-    for k in range(5, 400, 1):
-        dt, info, err = timed(gsr.solve_opts(itnlim=k, fixed_iters=True))
-        if err <= 1e-8:
-            k64 = k
-            best64 = min(timed(gsr.solve_opts(itnlim=k, fixed_iters=True))[0] for _ in range(3))
-            break
-    log(f"binary64: {k64} iterations to 1e-8, {best64:.4f} s")
-    # binary32 coefficients + refinement: first inner solve to its floor, then short ones
-    pre = timed(gsr.solve_opts(itnlim=k64 + 20, fixed_iters=True, precision=gsr.GSR_F32V,
-                               max_refine=1))[2]
-    # (k1 steps in the first inner solve, then one correction solve of k2 steps): for each k1
-    # the fewest k2 that reach 1e-8; the pair with the fewest steps in total is timed
-    best_pair, best_total = None, None
-    for k1 in range(max(3, k64 // 4), 2 * k64):
-        if best_total is not None and k1 >= best_total:
-            break
-        for k2 in range(1, k1 + 1):
-            if best_total is not None and k1 + k2 >= best_total:
-                break
-            o = gsr.solve_opts(itnlim=k1, fixed_iters=True, precision=gsr.GSR_F32V,
-                               max_refine=2, refine_tol=0.0, refine_itnlim=k2)
-            if timed(o)[2] <= 1e-8:
-                best_pair, best_total = (k1, k2), k1 + k2
-                break
-    best32, cfg32 = None, None
-    if best_pair is not None:
-        k1, k2 = best_pair
-        o = gsr.solve_opts(itnlim=k1, fixed_iters=True, precision=gsr.GSR_F32V, max_refine=2,
-                           refine_tol=0.0, refine_itnlim=k2)
-        dt, info, err = timed(o)
-        best32 = min(timed(o)[0] for _ in range(3))
-        cfg32 = {"inner_iterations_first": k1, "inner_iterations_later": k2,
-                 "outer_steps": info["n_refine"], "total_iterations": info["itn"],
-                 "rel_err": err}
-    log(f"binary32+refinement: {cfg32}, {best32}")
+    def best_of(opts, reps=3):
+        runs = [run(opts) for _ in range(reps)]
+        return min(r[0] for r in runs), runs[-1][1], runs[-1][2]
+
+    # (1) tolerances fixed in advance
+    a = APRIORI
+    o64 = gsr.solve_opts(itnlim=a["itnlim"], fixed_iters=False, atol=a["atol"], btol=a["btol"])
+    o32 = gsr.solve_opts(itnlim=a["itnlim"], fixed_iters=False, atol=a["atol"], btol=a["btol"],
+                         precision=gsr.GSR_F32V, max_refine=a["max_refine"],
+                         refine_tol=a["refine_tol"], refine_first_tol=a["refine_first_tol"])
+    run(o64), run(o32)  # graphs captured outside the timed runs
+    t64, i64, e64 = best_of(o64)
+    t32, i32, e32 = best_of(o32)
+    apriori = {"settings": dict(a, target_rel_err=TARGET_REL_ERR),
+               "f64": {"s": round(t64, 4), "itn": i64["itn"], "istop": i64["istop"],
+                       "rel_err": e64},
+               "f32_refined": {"s": round(t32, 4), "itn": i32["itn"],
+                               "n_refine": i32["n_refine"], "rel_err": e32},
+               "speedup": round(t64 / t32, 4),
+               "both_reach_target": bool(e64 <= TARGET_REL_ERR and e32 <= TARGET_REL_ERR)}
+    log(f"precision, a priori: {apriori}")
+
+    # (2) fixed schedules searched against the reference (error decreases with the steps)
+    def err_fixed(k):
+        return run(gsr.solve_opts(itnlim=k, fixed_iters=True))[2]
+
+    def fewest(ok, lo, hi):
+        """smallest k in [lo, hi] with ok(k) (ok monotone), or None"""
+        if not ok(hi):
+            return None
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if ok(mid):
+                hi = mid
+            else:
+                lo = mid + 1
+        return lo
+
+    k64 = fewest(lambda k: err_fixed(k) <= TARGET_REL_ERR, 1, max(8, i64["itn"] + 20))
+    sched = {"f64": None, "f32_refined": None, "speedup": None}
+    if k64 is not None:
+        tk64 = best_of(gsr.solve_opts(itnlim=k64, fixed_iters=True))[0]
+        sched["f64"] = {"iterations": k64, "s": round(tk64, 4)}
+
+        def o_pair(k1, k2):
+            return gsr.solve_opts(itnlim=k1, fixed_iters=True, precision=gsr.GSR_F32V,
+                                  max_refine=2, refine_tol=0.0, refine_itnlim=k2)
+
+        best = None
+        for k1 in sorted({max(2, k64 // 3), max(2, k64 // 2), max(2, (2 * k64) // 3),
+                          max(2, k64 - 4)}):
+            k2 = fewest(lambda k: run(o_pair(k1, k))[2] <= TARGET_REL_ERR, 1, k64 + 10)
+            if k2 is not None and (best is None or k1 + k2 < sum(best)):
+                best = (k1, k2)
+        if best is not None:
+            t, info, err = best_of(o_pair(*best))
+            sched["f32_refined"] = {"first_iterations": best[0], "later_iterations": best[1],
+                                    "total_iterations": info["itn"], "s": round(t, 4),
+                                    "rel_err": err}
+            sched["speedup"] = round(tk64 / t, 4)
+    log(f"precision, searched fixed schedules: {sched}")
+
+    # binary32 storage error before any correction: one converged binary32 inner solve
+    pre = run(gsr.solve_opts(itnlim=2000, fixed_iters=False, atol=1e-14, btol=1e-14,
+                             precision=gsr.GSR_F32V, max_refine=1))[2]
     # per-iteration pass times of both precisions (events around each pass)
     passes = {}
-    for name, prec in (("f64", gsr.GSR_F64), ("f32_values", gsr.GSR_F32V)):
-        info = timed(gsr.solve_opts(itnlim=10, fixed_iters=True, precision=prec, max_refine=1,
-                                    profile=True))[1]
-        passes[name] = {"pass1_ms": round(info["ms_pass1"], 4),
-                        "pass2_ms": round(info["ms_pass2"], 4)}
-    log(f"per-iteration passes: {passes}")
-    h.close()
-    return {
-        "metric": "time to 1e-8 relative solution error (binary64 vs binary32-stored + refined)",
-        "value": round(best64 / best32, 4) if best32 else None,
-        "unit": "speedup (binary64 time / refined time)",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "dtype": "f64 / f32-stored",
-        "data": "synthetic",
-        "config": {"workload": shape.name, "rows": m, "cols": n},
-        "f64": {"iterations": k64, "seconds": best64},
-        "f32_refined": {"seconds": best32, **(cfg32 or {})},
-        "pre_refinement_rel_err": pre,
-        "reference_iterations": ref["itn"],
-        "passes_per_iteration": passes,
-    }
+    for name, prec, vb in (("f64", gsr.GSR_F64, 8), ("f32_values", gsr.GSR_F32V, 4)):
+        info = run(gsr.solve_opts(itnlim=10, fixed_iters=True, precision=prec, max_refine=1,
+                                  profile=True))[1]
+        pb = pass_bytes(m, n, shape, bool(info["fused"]), value_bytes=vb)
+        passes[name] = {}
+        for key, ms in (("pass1", info["ms_pass1"]), ("pass2", info["ms_pass2"])):
+            gbps = pb[key] / (ms * 1e-3) / 1e9
+            passes[name][key] = {"ms": round(ms, 4), "bytes": pb[key], "GBps": round(gbps, 1),
+                                 "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+    log(f"precision, per-iteration passes: {passes}")
+    return {"target_rel_err": TARGET_REL_ERR,
+            "reference": {"itn": ref["itn"], "istop": ref["istop"], "atol": 1e-15},
+            "a_priori_tolerances": apriori,
+            "searched_fixed_schedule_bound": sched,
+            "pre_refinement_rel_err": pre,
+            "passes_per_iteration": passes}
 
 
 def form_batch(args) -> dict:
@@ -440,10 +494,11 @@ def form_grad(args) -> dict:
     st = gad.Structure(t["star"], t["att"], t["instr"], shape.n_stars, shape.n_dfa,
                        shape.n_instr)
     from paper_2212_11675_amd import gsr
-    h = gsr.gsr_lsqr_setup(st.dims(), t["vals"], t["star"], t["att"], t["instr"])
+    # the structure's handle, set up once (outside the timed steps); b = A x_true + e
+    st.load(t["vals"])
+    h = st.handle()
     b = torch.from_numpy(synth.noise(shape)).to(dev)
     gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
-    h.close()
     xr = torch.from_numpy(synth.x_ref(shape)).to(dev)
 
     def step():
@@ -463,8 +518,18 @@ def form_grad(args) -> dict:
         loss = step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # what a training step adds when the coefficients changed: the handle's copies and
+    # preconditioner rebuilt in place
+    vnew = t["vals"].detach().clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gsr.gsr_update_values(h, vnew)
+    torch.cuda.synchronize()
+    t_upd = time.perf_counter() - t0
+    st.close()
     return {
         "metric": "forward+backward through PC-LSQR (adjoint LSQR), seconds per step",
+        "update_values_s": round(t_upd, 4),
         "value": round(dt, 4), "unit": "s/step", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
         "config": {"workload": shape.name, "rows": d["n_rows"], "cols": shape.n_cols,
@@ -528,25 +593,40 @@ def form_var(args) -> dict:
     }
 
 
+HEADLINE_WORKLOAD = "stars5e6_obs40_dfa1e5_instr1e4"
+SECOND_WORKLOAD = "stars1e6_obs20_dfa3e4_instr6e3"
+CPU_SAMPLE_STARS = 1_000_000  # oracle sample: rows of the first 1e6 stars (4e7 rows)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--iters", type=int, default=200)
-    ap.add_argument("--workload", default="stars1e6_obs20_dfa3e4_instr6e3")
-    ap.add_argument("--form", default="f64",
-                    choices=["f64", "precision", "batch", "grad", "var"],
-                    help="f64: the headline binary64 solve; the others print their own line")
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--workload", default=None,
+                    help=f"default {HEADLINE_WORKLOAD} ({SECOND_WORKLOAD} for --form grad/var)")
+    ap.add_argument("--form", default="f64", choices=["f64", "batch", "grad", "var"],
+                    help="f64: the headline binary64 solve with the precision comparison; "
+                         "the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the binary32-stored + refined comparison")
+    ap.add_argument("--cpu-sample-stars", type=int, default=CPU_SAMPLE_STARS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="only set up the system and run one profiled solve of --iters "
+                         "iterations (every product launch does its full work): the command "
+                         "the rocprofv3 --pmc runs profile")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "CMD"),
                     help="write profiles/<KERNEL>_<workload>_hbm_traffic.txt from two rocprofv3 "
                          "--pmc outputs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--no-events", action="store_true",
                     help="replay the captured iteration graph instead of event-bracketed launches")
     args = ap.parse_args()
+    if args.workload is None:
+        args.workload = HEADLINE_WORKLOAD if args.form in ("f64", "batch") else SECOND_WORKLOAD
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU split of the path is a design note, not a measured configuration",
@@ -567,8 +647,7 @@ def main() -> None:
         log("copy calibration: 3 copies of 1 GiB (1073741824 B read + written each)")
         del src, dst
     if args.form != "f64":
-        fn = {"precision": form_precision, "batch": form_batch, "grad": form_grad,
-              "var": form_var}[args.form]
+        fn = {"batch": form_batch, "grad": form_grad, "var": form_var}[args.form]
         print(json.dumps(fn(args)), flush=True)
         return
 
@@ -581,24 +660,18 @@ def main() -> None:
     shape = synth.WORKLOADS[args.workload]
     t_gen = time.perf_counter()
     dev = torch.device("cuda:0")
-    if args.no_cpu_baseline:  # host copy not needed: generate and upload in row chunks
-        sysd = None
-        t, d = upload_system(shape)
-    else:
-        sysd = synth.system(shape)
-        d = sysd["dims"]
-        t = {k: torch.from_numpy(sysd[k]).to(dev) for k in ("vals", "star", "att", "instr")}
+    t, d = upload_system(shape)
     m, n = d["n_rows"], shape.n_cols
     x_true = torch.from_numpy(synth.x_true(shape)).to(dev)
     noise = torch.from_numpy(synth.noise(shape)).to(dev)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
-    print(f"[bench] {shape.name}: {m} rows, {n} cols, inputs on device in {t_gen:.1f} s",
-          file=sys.stderr, flush=True)
+    log(f"{shape.name}: {m} rows, {n} cols, inputs on device in {t_gen:.1f} s")
 
+    precision = not (args.no_precision or args.counter_run)
     t_setup = time.perf_counter()
     h = gsr.gsr_lsqr_setup(gsr.make_dims(m, d["n_stars"], d["n_dfa"], d["n_instr"]), t["vals"],
-                           t["star"], t["att"], t["instr"])
+                           t["star"], t["att"], t["instr"], build_f32=precision)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     # right-hand side b = A x_true + e, formed by the library's own product
@@ -606,6 +679,13 @@ def main() -> None:
     gsr.gsr_aprod1(h, x_true, b)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     opts = gsr.solve_opts(itnlim=args.iters, fixed_iters=True, profile=not args.no_events)
+    if args.counter_run:
+        info = gsr.gsr_lsqr_solve(h, b, x, gsr.solve_opts(itnlim=args.iters, fixed_iters=True,
+                                                           profile=True))
+        torch.cuda.synchronize()
+        log(f"counter run: one profiled solve of {info['itn']} iterations")
+        h.close()
+        return
 
     for _ in range(args.warmup):
         gsr.gsr_lsqr_solve(h, b, x, opts)
@@ -622,9 +702,8 @@ def main() -> None:
     value = iters / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
     rel_err = float(torch.linalg.norm(x - x_true) / torch.linalg.norm(x_true))
-    print(f"[bench] {args.steps} solves x {args.iters} iterations: {elapsed:.3f} s, "
-          f"{value:.1f} it/s, ||x - x_true||/||x_true|| = {rel_err:.2e}", file=sys.stderr,
-          flush=True)
+    log(f"{args.steps} solves x {args.iters} iterations: {elapsed:.3f} s, {value:.1f} it/s, "
+        f"||x - x_true||/||x_true|| = {rel_err:.2e}")
 
     roofline = None
     extra = {}
@@ -642,26 +721,26 @@ def main() -> None:
         copy_gbps = copy_bandwidth()
         roofline = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBPS, 4),
-                    "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(gb / copy_gbps, 4),
                     "traffic": stored_traffic(names[dom], shape.name,
                                               pb["pass1" if dom == 0 else "pass2"]),
+                    "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(gb / copy_gbps, 4),
                     "kernel": names[dom], "ms_per_launch": round(msd, 4),
                     "algorithmic_bytes_per_launch": pb["pass1" if dom == 0 else "pass2"]}
         ab = algorithmic_bytes(m, n)
+        att_traffic = stored_traffic("k_aprod2_att", shape.name, pb["pass2"]) if fused else None
         extra["passes"] = {
             "fused_row_pass": fused,
             "pass1": {"kernels": names[0], "ms": round(ms1, 4), "bytes": pb["pass1"],
                       "GBps": round(gbps1, 1), "frac_of_peak": round(gbps1 / HBM_PEAK_GBPS, 4)},
             "pass2": {"kernels": names[1], "ms": round(ms2, 4), "bytes": pb["pass2"],
-                      "GBps": round(gbps2, 1), "frac_of_peak": round(gbps2 / HBM_PEAK_GBPS, 4)},
+                      "GBps": round(gbps2, 1), "frac_of_peak": round(gbps2 / HBM_PEAK_GBPS, 4),
+                      "attitude_pass_traffic": att_traffic},
             # the two products as separate operations would move aprod1 + aprod2 bytes;
             # the fused schedule reads each row once, so this can exceed the peak
             "aprod1_plus_aprod2_bytes": ab["aprod1"] + ab["aprod2"],
             "aprod1_plus_aprod2_equivalent_GBps": round(
                 (ab["aprod1"] + ab["aprod2"]) / ((ms1 + ms2) * 1e-3) / 1e9, 1),
         }
-
-    if not args.no_events:
         # the same solves replayed from the captured iteration graph, without the events the
         # timed region records around every pass (outside the timed region; context only)
         gopts = gsr.solve_opts(itnlim=args.iters, fixed_iters=True)
@@ -674,9 +753,14 @@ def main() -> None:
         extra["iterations_per_s_graph_replay"] = round(
             args.steps * args.iters / (time.perf_counter() - t0), 3)
 
+    if precision:
+        extra["precision_form"] = precision_compare(h, b, shape, m, n)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(shape, sysd, b.cpu().numpy())
+        ns = min(args.cpu_sample_stars, shape.n_stars)
+        cpu = cpu_baseline(shape, b[: int(shape.row_ptr()[ns])].cpu().numpy(), ns)
+        log(f"cpu baseline: {cpu}")
 
     out = {
         "metric": METRIC,
@@ -693,8 +777,9 @@ def main() -> None:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": shape.name, "rows": m, "cols": n, "nnz": 24 * m,
+                   "step": f"one binary64 PC-LSQR solve of {args.iters} fixed iterations",
                    "iterations_per_step": args.iters, "precision": "binary64 PC-LSQR",
-                   "setup_s": round(t_setup, 3)},
+                   "setup_s": round(t_setup, 3), "inputs_s": round(t_gen, 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         **extra,

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define GSR_ABI_VERSION 3
+#define GSR_ABI_VERSION 4
 
 typedef enum gsr_status {
     GSR_OK = 0,
@@ -97,6 +97,11 @@ typedef struct gsr_solve_opts {
     int32_t refine_itnlim; /* GSR_F32V: iteration limit of the correction solves after the
                             first (0 = itnlim)                                          */
     int32_t reserved;
+    double refine_first_tol; /* GSR_F32V, fixed_iters = 0: atol = btol of the first inner
+                            solve (0 = atol, btol).  Its result cannot come closer to the
+                            binary64 solution than the binary32 rounding of the
+                            coefficients allows, so it may stop early; the correction
+                            solves use atol, btol                                         */
 } gsr_solve_opts;
 
 typedef struct gsr_solve_info {
@@ -160,15 +165,18 @@ gsr_status gsr_lsqr_setup(const gsr_dims *dims, const double *vals, const int32_
 /* Release the handle and everything it owns.  NULL is accepted. */
 gsr_status gsr_destroy(gsr_handle *h);
 
-/* Sizes of the handle's system (host out-pointers, any may be NULL). */
+/* Sizes of the handle's system (host out-pointers, any may be NULL): rows of the operator
+ * (n_rows plus the constraint rows of gsr_set_constraints) and unknowns. */
 gsr_status gsr_get_size(const gsr_handle *h, int64_t *n_rows, int64_t *n_cols);
 
 /* aprod mode 1 (Section 3; Algorithm 1):  y[i] += sum_k A[i,k] x[col(i,k)].
- *   x [n_cols], y [n_rows], binary64; y is read and written.  Unpreconditioned A. */
+ *   x [n_cols], y [n_rows], binary64; y is read and written.  Unpreconditioned A.
+ *   With constraint rows (gsr_set_constraints) y has n_rows + n_con entries, y_c += C x last. */
 gsr_status gsr_aprod1(gsr_handle *h, const double *x, double *y, void *stream);
 
 /* aprod mode 2 (Section 3; Algorithm 2):  x[col(i,k)] += A[i,k] y[i]  (x += A^T y).
  *   y [n_rows], x [n_cols], binary64; x is read and written.  Unpreconditioned A.
+ *   With constraint rows y has n_rows + n_con entries and x += C^T y_c as well.
  *   Summation order varies between calls (device atomics): results agree to rounding. */
 gsr_status gsr_aprod2(gsr_handle *h, const double *y, double *x, void *stream);
 
@@ -210,18 +218,22 @@ gsr_status gsr_lsqr_solve_var(gsr_handle *h, const double *b, double *x, double 
                               const gsr_solve_opts *opts, gsr_solve_info *info, void *stream);
 
 /*
- * The binary64 PC-LSQR of gsr_lsqr_solve (Section 3, flowchart paragraph), stream-ordered:
- * every launch goes to `stream`, in order, with no host synchronization, no allocation and
- * no memset, so the call may be captured into a HIP graph (the graph then repeats the solve
- * on the current contents of b).  All opts->itnlim iterations are enqueued one kernel at a
+ * The PC-LSQR of gsr_lsqr_solve (Section 3, flowchart paragraph), stream-ordered: every
+ * launch goes to `stream`, in order, with no host synchronization, no allocation and no
+ * memset, so the call may be captured into a HIP graph (the graph then repeats the solve on
+ * the current contents of b).  All opts->itnlim iterations are enqueued one kernel at a
  * time; once the device-side stop flag is set (fixed_iters = 0, or an exact breakdown) the
- * remaining launches return at once.  When the stream reaches the end, x [n_cols] holds the
- * solution and *info_dev (DEVICE memory, one gsr_solve_info) the solve information:
- * ms_pass1 = ms_pass2 = 0 and n_pass = 0; a non-finite value sets info_dev->nonfinite
- * instead of returning GSR_E_BREAKDOWN.  opts->precision must be GSR_F64 and opts->profile 0
- * (GSR_E_UNSUPPORTED / GSR_E_INVAL otherwise).  The workspaces it uses belong to the handle
- * and are allocated by gsr_lsqr_setup: calls on one handle must not overlap (nor overlap
- * any other solve on the handle).
+ * remaining launches return at once.  GSR_F32V (setup with build_f32 = 1, else
+ * GSR_E_UNSUPPORTED): all opts->max_refine correction steps are enqueued, each with its
+ * inner solve, the update x += d_k and the test ||d_k|| <= refine_tol ||x|| taken on the
+ * device; once a test ends the loop, the launches of the later steps return at once.
+ * When the stream reaches the end, x [n_cols] holds the solution and *info_dev (DEVICE
+ * memory, one gsr_solve_info) the solve information (itn summed over the inner solves,
+ * n_refine the correction steps taken; ms_pass1 = ms_pass2 = 0 and n_pass = 0); a
+ * non-finite value sets info_dev->nonfinite instead of returning GSR_E_BREAKDOWN.
+ * opts->profile must be 0 (GSR_E_INVAL).  The workspaces it uses belong to the handle and
+ * are allocated by gsr_lsqr_setup: calls on one handle must not overlap (nor overlap any
+ * other solve on the handle).
  */
 gsr_status gsr_lsqr_solve_async(gsr_handle *h, const double *b, double *x,
                                 const gsr_solve_opts *opts, gsr_solve_info *info_dev,
@@ -239,10 +251,55 @@ gsr_status gsr_lsqr_solve_adjoint(gsr_handle *h, const double *g, double *mu, do
                                   void *stream);
 
 /* dL/dvals[i*24+k] = r[i] lam[col(i,k)] - mu[i] x[col(i,k)]  (differentiating the normal
- * equations A^T A x = A^T b), with r = b - A x*.  r, mu [n_rows]; x, lam [n_cols];
- * dvals [n_rows*24] output. */
+ * equations A^T A x = A^T b), with r = b - A x*.  r, mu [n_rows] (with constraint rows
+ * [n_rows + n_con], of which the first n_rows are read); x, lam [n_cols]; dvals [n_rows*24]
+ * output: the gradient of the observation coefficients only. */
 gsr_status gsr_grad_vals(gsr_handle *h, const double *r, const double *mu, const double *x,
                          const double *lam, double *dvals, void *stream);
+
+/*
+ * New coefficient values for the handle's system, same index map (star, att, instr) and
+ * sizes: the library's copies of the coefficients (row tiles, the copy ordered by attitude
+ * start, the binary32 copies when built) are rebuilt in place and the preconditioner is
+ * recomputed (Section 2), without the sort and the allocations of gsr_lsqr_setup.  For
+ * callers that change the coefficients between solves (the differentiation form's training
+ * loop).
+ *   vals  [n_rows*24] binary64 (device), 16-byte aligned; referenced from now on in place of
+ *         the array given to gsr_lsqr_setup (or to the previous call), under the same
+ *         contract.
+ * Must not overlap any other call on the handle.  Synchronizes `stream`.  Errors:
+ * GSR_E_INVAL; GSR_E_LAYOUT if a column became all-zero and the handle was set up without
+ * allow_empty_cols (the new values are in place all the same, with p = 0 for that column);
+ * GSR_E_HIP.
+ */
+gsr_status gsr_update_values(gsr_handle *h, const double *vals, void *stream);
+
+/*
+ * Constraint equations (Section 3: the extra equations a unique solution needs; the
+ * "constraints computation" region that closes Algorithms 1 and 2).  Attaches n_con sparse
+ * rows C, in compressed row form, below the n_rows observation rows: from this call on every
+ * product, residual and solve of the handle acts on the stacked [A; C], which has
+ * n_rows + n_con rows (gsr_get_size reports them).  Row-space vectors -- y of the products,
+ * b and r of gsr_residual, b of the solves, mu of the adjoint solve -- then hold
+ * n_rows + n_con entries, the constraint rows last (their right-hand side c at the end of b).
+ * The preconditioner is recomputed over [A; C]; the constraint coefficients stay binary64 in
+ * the GSR_F32V form.
+ *   n_con   rows of C; 0 removes the handle's constraint rows.
+ *   ptr     [n_con + 1] int64 (device), ptr[0] = 0, non-decreasing: row k holds the entries
+ *           ptr[k] .. ptr[k+1]-1 (a row may be empty).
+ *   col     [ptr[n_con]] int64 (device), absolute columns in [0, n_cols); a column repeated
+ *           within a row adds up.
+ *   val     [ptr[n_con]] binary64 (device) coefficients.
+ * The arrays are referenced, not copied (the library builds its own copy grouped by column):
+ * they must stay valid and unchanged until the next gsr_set_constraints or gsr_destroy.  The
+ * solve workspaces are reallocated (the row count changes), so the call must not overlap any
+ * other call on the handle.  The batched API has no constraint rows.  Synchronizes `stream`.
+ * Errors: GSR_E_INVAL, GSR_E_LAYOUT (ptr[0] != 0, ptr decreasing, column out of range),
+ * GSR_E_UNSUPPORTED (n_con or ptr[n_con] above 2^31-1), GSR_E_NOMEM, GSR_E_HIP; after an
+ * error the handle has no constraint rows.
+ */
+gsr_status gsr_set_constraints(gsr_handle *h, int64_t n_con, const int64_t *ptr,
+                               const int64_t *col, const double *val, void *stream);
 
 /* ---- batching: many independent systems, k right-hand sides each ------------------------ */
 
@@ -277,7 +334,9 @@ gsr_status gsr_batch_aprod2(gsr_batch *b, const double *Y, double *X, void *stre
 
 /* PC-LSQR of every (system, rhs) pair: B [sum rows * k], X [sum cols * k] output, both
  * RHS-minor; each pair has its own scalars and stopping state.  info host [n_sys*k] or
- * NULL (entry s*k + j).  Synchronizes `stream`. */
+ * NULL (entry s*k + j).  A non-finite value in any pair returns GSR_E_BREAKDOWN; info is
+ * filled all the same and info[s*k + j].nonfinite names the pairs that broke down (the
+ * others ran on to their own stop).  Synchronizes `stream`. */
 gsr_status gsr_batch_solve(gsr_batch *b, const double *B, double *X, const gsr_solve_opts *opts,
                            gsr_solve_info *info, void *stream);
 

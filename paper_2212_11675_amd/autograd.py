@@ -10,7 +10,7 @@ runs in the HIP library; this module only marshals tensors.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import torch
 
@@ -20,7 +20,14 @@ from . import gsr
 @dataclass
 class Structure:
     """Index map of a system (Section 3): star number, attitude start and instrumental
-    indices per row, as int32 CUDA tensors, plus the section sizes."""
+    indices per row, as int32 CUDA tensors, plus the section sizes.
+
+    The structure owns one library handle, set up at the first solve and reused after it:
+    every later solve brings its coefficients into the handle with gsr_update_values (the
+    handle's copies and preconditioner rebuilt in place, no sort, no allocation) -- whether
+    they changed or not cannot be told reliably (writes through .data leave no trace) -- and a
+    backward pass does the same when another solve used the handle after its forward.
+    close() releases the handle; so does dropping the structure."""
 
     star: torch.Tensor
     att: torch.Tensor
@@ -28,6 +35,9 @@ class Structure:
     n_stars: int
     n_dfa: int
     n_instr: int
+    _handle: gsr.Handle | None = field(default=None, init=False, repr=False)
+    _gen: int = field(default=0, init=False, repr=False)  # solves that loaded values
+    _vals: torch.Tensor | None = field(default=None, init=False, repr=False)
 
     @property
     def n_rows(self) -> int:
@@ -40,18 +50,49 @@ class Structure:
     def dims(self) -> gsr.Dims:
         return gsr.make_dims(self.n_rows, self.n_stars, self.n_dfa, self.n_instr)
 
+    def load(self, vals: torch.Tensor) -> int:
+        """Bring the coefficients `vals` (contiguous float64 CUDA tensor) into the handle
+        (set up at the first call); returns the generation that identifies this load.  The
+        tensor is referenced, not copied: the structure keeps it alive while it is loaded."""
+        if self._handle is None:
+            self._handle = gsr.gsr_lsqr_setup(self.dims(), vals, self.star, self.att,
+                                              self.instr, allow_empty_cols=True)
+        else:
+            gsr.gsr_update_values(self._handle, vals)
+        self._vals = vals
+        self._gen += 1
+        return self._gen
+
+    def handle(self, vals: torch.Tensor | None = None, gen: int | None = None) -> gsr.Handle:
+        """The handle; with `vals` and the generation `gen` of an earlier load, the values
+        are loaded again unless that load is still the current one."""
+        if vals is not None and (self._handle is None or gen != self._gen):
+            self.load(vals)
+        return self._handle
+
+    def close(self):
+        if self._handle is not None:
+            self._handle.close()
+        self._handle, self._vals = None, None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class LstsqSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vals, b, structure: Structure, itnlim: int, atol: float, btol: float):
         vals_c = vals.detach().contiguous()
         b_c = b.detach().contiguous()
-        h = gsr.gsr_lsqr_setup(structure.dims(), vals_c, structure.star, structure.att,
-                               structure.instr, allow_empty_cols=True)
+        ctx.gen = structure.load(vals_c)
+        h = structure.handle()
         opts = gsr.solve_opts(itnlim=itnlim, fixed_iters=False, atol=atol, btol=btol)
         x = torch.empty(structure.n_cols, dtype=torch.float64, device=vals.device)
         info = gsr.gsr_lsqr_solve(h, b_c, x, opts)
-        ctx.h = h
+        ctx.structure = structure
         ctx.opts = opts
         ctx.info = info
         ctx.save_for_backward(vals_c, b_c, x)
@@ -60,7 +101,8 @@ class LstsqSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         vals_c, b_c, x = ctx.saved_tensors
-        h = ctx.h
+        # the coefficients of this forward, loaded again if another solve used the handle since
+        h = ctx.structure.handle(vals_c, ctx.gen)
         g = g.detach().contiguous().to(torch.float64)
         m, n = h.m, h.n
         mu = torch.empty(m, dtype=torch.float64, device=g.device)
@@ -73,7 +115,6 @@ class LstsqSolve(torch.autograd.Function):
             grad_vals = torch.empty(24 * m, dtype=torch.float64, device=g.device)
             gsr.gsr_grad_vals(h, r, mu, x, lam, grad_vals)
         grad_b = mu if ctx.needs_input_grad[1] else None
-        # the handle stays open (backward may run again); it is released with the graph
         return grad_vals, grad_b, None, None, None, None
 
 

@@ -1544,6 +1544,8 @@ gsr_status gsr_batch_solve(gsr_batch* b, const double* B, double* X, const gsr_s
             f.itn = t.itn;
             f.istop = t.istop;
             f.n_refine = 1;
+            f.nonfinite = t.nonfinite;  // which pair broke down, beside the status returned
+            f.fused = 1;                // the batched row pass is always the fused one
             f.rnorm = t.rnorm;
             f.arnorm = t.arnorm;
             f.anorm = std::sqrt(t.anorm2);

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -18,6 +19,7 @@
 #include "gsr_internal.hpp"
 #include "kernels.hpp"
 #include "products.hpp"
+#include "constraints.hpp"
 
 #include <hipcub/hipcub.hpp>
 
@@ -138,6 +140,7 @@ struct gsr_handle {
     size_t lds1_bytes = 0, lds2_bytes = 0;
     // fused row pass (aprod 1 + star-ordered part of aprod 2), used when n_instr fits LDS
     int fused = 0, G12 = 1, chunk12 = 16;
+    int allow_empty = 0;           // setup option: all-zero columns accepted
     size_t lds12_bytes = 0;
     // row tiles of the fused pass (coefficients per precision, packed indices)
     int64_t ntiles = 0;
@@ -145,10 +148,26 @@ struct gsr_handle {
     float* tiles32 = nullptr;
     LsqrWork fwd64, fwd32, trans;  // forward (per precision) and transposed recurrences
     LsqrWork fwd64v;               // forward recurrence with the variance estimate
-    double *dx = nullptr, *r = nullptr;  // refinement
-    double* ref_part = nullptr;          // [2 Gn] device partial norms of the refinement step
-    double* ref_host = nullptr;          // [2 Gn] pinned host copy
+    // residual correction of the precision form (allocated at setup with the binary32 copy)
+    double *dx = nullptr, *r = nullptr;  // [n] correction, [m] residual
+    double* ref_part = nullptr;          // [2 Gn] partial norms of a correction step
+    RefState* ref = nullptr;             // loop state (device)
+    RefState* ref_host = nullptr;        // pinned mirror
     hipStream_t cap = nullptr;     // capture stream
+    // constraint rows below the observation rows (gsr_set_constraints)
+    int64_t n_con = 0, nnz_c = 0;
+    const int64_t *cptr = nullptr, *ccol = nullptr;  // caller's rows (device)
+    const double* cval = nullptr;
+    int32_t* crow = nullptr;     // [nnz_c] row of each entry
+    double* cacc = nullptr;      // [n_con] dot products (kept zero between uses)
+    int64_t ncu = 0;             // distinct columns of C
+    int64_t *cu_col = nullptr, *cu_ptr = nullptr;  // [ncu], [ncu + 1]
+    int32_t* cu_row = nullptr;   // [nnz_c] entries grouped by column: row, value
+    double* cu_val = nullptr;
+    int Gcon = 1;
+    int64_t con_per_block = 0;
+    int nc1 = 0;                 // 1 when constraint rows exist (one more partial-sum slot)
+    int64_t rows() const { return g.m + n_con; }  // rows of the stacked operator
 };
 
 namespace {
@@ -210,15 +229,41 @@ constexpr int kBlock2t = 256;  // aprod 2, attitude pass
 const double* tiles_of(const gsr_handle* h, const double*) { return h->tiles64; }
 const float* tiles_of(const gsr_handle* h, const float*) { return h->tiles32; }
 
-// y (op)= A xx, from the row tiles when the library built them for this precision
+// Constraint rows.  y_c (op)= C x with the operation of k_con_fin (LSQR modes write their
+// partial sums to part[0] (and part[stride], ... with PENDING)).
+template <int MODE, bool TRANS = false, bool PENDING = false>
+void launch_con_a1(const gsr_handle* h, const double* x, double* yc, const double* bc,
+                   double* part, int stride, double* wc, double* zc, hipStream_t s,
+                   const int32_t* gate = nullptr) {
+    if (!h->n_con) return;
+    if (h->nnz_c > 0)
+        hipLaunchKernelGGL(k_con_dot, dim3(h->Gcon), dim3(kConBlock), 0, s, h->nnz_c,
+                           h->con_per_block, h->crow, h->ccol, h->cval, x, h->cacc, h->st,
+                           (int)(MODE == CON_LSQR), gate);
+    hipLaunchKernelGGL((k_con_fin<MODE, TRANS, PENDING>), dim3(1), dim3(kConBlock), 0, s,
+                       h->n_con, h->cacc, yc, bc, h->st, part, stride, wc, zc, gate);
+}
+
+// x += C^T y_c (SQ: the squared coefficients, for the column norms; y_c unused)
+template <bool SQ>
+void launch_con_a2(const gsr_handle* h, const double* yc, double* x, int check_stop,
+                   hipStream_t s) {
+    if (!h->n_con || !h->ncu) return;
+    hipLaunchKernelGGL((k_con_a2<SQ>), dim3(grid_for(h->ncu, kConBlock, kVecBlocksMax)),
+                       dim3(kConBlock), 0, s, h->ncu, h->cu_col, h->cu_ptr, h->cu_row, h->cu_val,
+                       yc, x, h->st, check_stop);
+}
+
+// y (op)= A xx, from the row tiles when the library built them for this precision; then the
+// constraint rows of y (binary64 coefficients in every precision)
 template <typename VT, int MODE>
 void launch_aprod1(const gsr_handle* h, const VT* vals, const double* xx, double* y,
-                   const double* b, hipStream_t s) {
+                   const double* b, hipStream_t s, const int32_t* gate = nullptr) {
     const VT* tiles = tiles_of(h, vals);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(h->G1), dim3(kBlock1), h->lds1_bytes, s, h->g, vals,
                            h->star, h->att, h->instr, tiles, xx, y, b, h->st,
-                           h->partA, h->chunk1);
+                           h->partA, h->chunk1, gate);
     };
     if (tiles && h->lds1)
         go(k_aprod1<VT, MODE, true, true>);
@@ -228,6 +273,14 @@ void launch_aprod1(const gsr_handle* h, const VT* vals, const double* xx, double
         go(k_aprod1<VT, MODE, false, true>);
     else
         go(k_aprod1<VT, MODE, false, false>);
+    const int64_t m = h->g.m;
+    if (MODE == A1_ADD)
+        launch_con_a1<CON_ADD>(h, xx, y + m, nullptr, nullptr, 0, nullptr, nullptr, s);
+    else if (MODE == A1_RESID)
+        launch_con_a1<CON_RESID>(h, xx, y + m, b + m, nullptr, 0, nullptr, nullptr, s, gate);
+    else  // the u-step's (or transposed v-step's) sum of squares continues in slot G1
+        launch_con_a1<CON_LSQR, MODE == A1_LSQR_T>(h, xx, y + m, nullptr, h->partA + h->G1, 0,
+                                                   nullptr, nullptr, s);
 }
 
 // x[ins0 .. glb0] += the blocks' instrumental/global sums in part_ig
@@ -249,6 +302,8 @@ void launch_aprod2(const gsr_handle* h, const VT* vals, const VT* attT, const do
     if (h->lds2) launch_reduce(h, h->G2s, x, (int)(MODE == A2_LSQR || MODE == A2_LSQR_T), s);
     hipLaunchKernelGGL((k_aprod2_att<VT, MODE>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
                        h->rowT, h->tT, y, x, h->st, h->chunk2t);
+    launch_con_a2<MODE == A2_SQ>(h, MODE == A2_SQ ? nullptr : y + g.m, x,
+                                 (int)(MODE == A2_LSQR || MODE == A2_LSQR_T), s);
 }
 
 // p = 1 / column norms of `vals`.  Synchronizes.
@@ -329,16 +384,23 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
                   double* parts, hipStream_t s, const IterEvents* ev, double* ww = nullptr,
                   double* zz = nullptr) {
     const Geo& g = h->g;
+    const int pstride = h->G12 + h->nc1;  // partial sums: G12 blocks, then the constraint rows
     if (ev) mark(TRANS ? ev->a2_begin : ev->a1_begin, s);
+    if (!INIT)  // constraint rows of the same step (with the transposed operator, their
+                // pending z/w update too)
+        launch_con_a1<CON_LSQR, TRANS, TRANS>(h, h->xt, u + g.m, nullptr, parts + h->G12,
+                                              pstride, TRANS ? ww + g.m : nullptr,
+                                              TRANS ? zz + g.m : nullptr, s);
     hipLaunchKernelGGL((k_aprod12<VT, kU12, TRANS, INIT>), dim3(h->G12), dim3(1024),
                        h->lds12_bytes, s,
                        g, tiles_of(h, vals), h->star, h->xt, u, s_acc, h->st, parts,
-                       h->part_ig, h->chunk12, ww, zz);
+                       h->part_ig, h->chunk12, pstride, ww, zz);
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
     if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
     launch_reduce(h, h->G12, s_acc, 1, s);
     hipLaunchKernelGGL((k_aprod2_att<VT, A2_LSQR>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
                        h->rowT, h->tT, u, s_acc, h->st, h->chunk2t);
+    launch_con_a2<false>(h, u + g.m, s_acc, 1, s);
     if (ev) mark(TRANS ? ev->a1_end : ev->a2_end, s);
 }
 
@@ -349,13 +411,15 @@ void fwd_iteration(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* a
     if (h->fused) {
         // one read of every row: beta u = A (p o v) - alpha u and s = A^T u~ (unnormalized)
         launch_fused<VT>(h, vals, attT, w.u, h->s, h->partA, s, ev);
-        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G12);
+        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA,
+                           h->G12 + h->nc1);
     } else {
         // beta u = A (p o v) - alpha u        (xt = p o v~ from the previous vector step)
         if (ev) mark(ev->a1_begin, s);
         launch_aprod1<VT, A1_LSQR>(h, vals, h->xt, w.u, nullptr, s);
         if (ev) mark(ev->a1_end, s);
-        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+        hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA,
+                           h->G1 + h->nc1);
         // s = A^T u~ (unnormalized)
         if (ev) mark(ev->a2_begin, s);
         launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
@@ -380,8 +444,9 @@ void trans_iteration(const gsr_handle* h, LsqrWork& w, hipStream_t s,
         hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn);
         // one read of every row: pending z/w update, alpha v = A D u - beta v, s = A^T v~
         launch_fused<double, true>(h, h->vals, h->attT64, w.v, h->s, h->partB, s, ev, w.w, w.z);
-        hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->G12,
-                           h->partB + h->G12, h->G12);
+        const int P = h->G12 + h->nc1;
+        hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, P,
+                           h->partB + P, P);
         return;
     }
     // beta u = D A^T v - alpha u
@@ -392,13 +457,13 @@ void trans_iteration(const gsr_handle* h, LsqrWork& w, hipStream_t s,
                        h->st, h->partA);
     hipLaunchKernelGGL(k_scal_beta, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn);
     // pending z/w update, then alpha v = A D u - beta v
-    hipLaunchKernelGGL(k_vec_zw, dim3(h->Gm), dim3(kBlock), 0, s, g.m, w.v, w.w, w.z, h->st,
-                       h->partB);
+    hipLaunchKernelGGL(k_vec_zw, dim3(h->Gm), dim3(kBlock), 0, s, h->rows(), w.v, w.w, w.z,
+                       h->st, h->partB);
     if (ev) mark(ev->a1_begin, s);
     launch_aprod1<double, A1_LSQR_T>(h, h->vals, h->xt, w.v, nullptr, s);
     if (ev) mark(ev->a1_end, s);
-    hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1,
-                       h->partB, h->Gm);
+    hipLaunchKernelGGL(k_scal_alpha, dim3(1), dim3(kBlock), 0, s, h->st, h->partA,
+                       h->G1 + h->nc1, h->partB, h->Gm);
 }
 
 // Profile mode: the iterations are launched one by one with events around the products;
@@ -528,11 +593,11 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
                      const double* p, const double* b, double* x, const gsr_solve_opts& o,
                      gsr_solve_info* info, hipStream_t s, double* var_out = nullptr) {
     const Geo& g = h->g;
-    GSR_TRY(ensure_work(w, g.m, g.n, VAR));
+    GSR_TRY(ensure_work(w, h->rows(), g.n, VAR));
     GSR_TRY(capture_graph(
         h, w, [&](hipStream_t cs) { fwd_iteration<VT, VAR>(h, w, vals, attT, p, cs); }));
     // beta_1 u_1 = b
-    hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
+    hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, h->rows(), b, nullptr,
                        w.u, nullptr, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gm,
                        o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim);
@@ -562,8 +627,10 @@ gsr_status fwd_solve(gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
 }
 
 // Solve information from the device state, written on the device (stream-ordered solve).
+// ref (may be NULL): the precision form's loop state, which gives the iteration count summed
+// over the correction steps and the number of steps.
 static __global__ void k_write_info(const LsqrState* __restrict__ st, gsr_solve_info* info,
-                                    int32_t fused) {
+                                    int32_t fused, const RefState* __restrict__ ref) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     gsr_solve_info f = {};
     f.itn = st->itn;
@@ -577,34 +644,92 @@ static __global__ void k_write_info(const LsqrState* __restrict__ st, gsr_solve_
     f.bnorm = st->bnorm;
     f.fused = fused;
     f.acond = sqrt(st->anorm2) * sqrt(st->ddnorm);
+    if (ref) {
+        f.itn = ref->itn;
+        f.n_refine = ref->n_refine;
+        f.nonfinite = ref->nonfinite | st->nonfinite;
+    }
     *info = f;
 }
 
-// The binary64 PC-LSQR with every iteration launched on `s` (no graph of its own, no host
-// synchronization, no allocation): capturable into the caller's graph.
-gsr_status fwd_solve_async(gsr_handle* h, const double* b, double* x, const gsr_solve_opts& o,
-                           gsr_solve_info* info_dev, hipStream_t s) {
+// One PC-LSQR solve with every iteration launched on `s` (no graph of its own, no host
+// synchronization, no allocation): capturable into the caller's graph.  All o.itnlim
+// iterations are enqueued; once the device stop flag is set the rest return at once.
+// gate (may be NULL): when *gate is set at the time the solve would start, it is not started.
+template <typename VT>
+void fwd_enqueue(const gsr_handle* h, LsqrWork& w, const VT* vals, const VT* attT,
+                 const double* p, const double* b, double* x, const gsr_solve_opts& o,
+                 hipStream_t s, const int32_t* gate) {
     const Geo& g = h->g;
-    LsqrWork& w = h->fwd64;
-    const double* p = h->p64;
-    hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, b, nullptr,
+    hipLaunchKernelGGL(k_copy_norm<false>, dim3(h->Gm), dim3(kBlock), 0, s, h->rows(), b, nullptr,
                        w.u, nullptr, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gm,
-                       o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim);
+                       o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim, gate);
     fill(h->s, g.n, 0.0, s);
     if (h->fused)
-        launch_fused<double, false, true>(h, h->vals, h->attT64, w.u, h->s, h->partB, s,
-                                          nullptr);
+        launch_fused<VT, false, true>(h, vals, attT, w.u, h->s, h->partB, s, nullptr);
     else
-        launch_aprod2<double, A2_LSQR>(h, h->vals, h->attT64, w.u, h->s, s);
+        launch_aprod2<VT, A2_LSQR>(h, vals, attT, w.u, h->s, s);
     hipLaunchKernelGGL((k_vec_v<true>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->s, p, w.v,
                        w.w, w.z, h->xt, h->st, h->partB, nullptr);
     hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->Gn);
-    for (int it = 0; it < o.itnlim; ++it)
-        fwd_iteration<double>(h, w, h->vals, h->attT64, p, s);
+    for (int it = 0; it < o.itnlim; ++it) fwd_iteration<VT>(h, w, vals, attT, p, s);
     hipLaunchKernelGGL((k_final<true>), dim3(h->Gn), dim3(kBlock), 0, s, g.n, p, w.z, w.w, w.v,
                        x, h->st);
-    hipLaunchKernelGGL(k_write_info, dim3(1), dim3(64), 0, s, h->st, info_dev, (int32_t)h->fused);
+}
+
+// Options of inner solve k of the precision form: the correction solves after the first may
+// have their own iteration limit, the first its own tolerance.
+gsr_solve_opts inner_opts(const gsr_solve_opts& o, int k) {
+    gsr_solve_opts ok = o;
+    if (k > 0 && o.refine_itnlim > 0) ok.itnlim = o.refine_itnlim;
+    if (k == 0 && o.refine_first_tol > 0.0) ok.atol = ok.btol = o.refine_first_tol;
+    return ok;
+}
+
+const int32_t* ref_stop_flag(const gsr_handle* h) {
+    return reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(h->ref) +
+                                            offsetof(RefState, stop));
+}
+
+// x += d_k, then the device-side test of the correction step (k_ref_check).
+void ref_step(const gsr_handle* h, double* x, const gsr_solve_opts& o, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_norms, dim3(h->Gn), dim3(kBlock), 0, s, h->g.n, h->dx, x,
+                       h->ref_part, h->ref);
+    hipLaunchKernelGGL(k_ref_check, dim3(1), dim3(kBlock), 0, s, h->ref, h->st, h->ref_part,
+                       h->Gn, o.refine_tol, o.max_refine);
+}
+
+// The binary64 PC-LSQR, stream-ordered.
+gsr_status fwd_solve_async(gsr_handle* h, const double* b, double* x, const gsr_solve_opts& o,
+                           gsr_solve_info* info_dev, hipStream_t s) {
+    fwd_enqueue<double>(h, h->fwd64, h->vals, h->attT64, h->p64, b, x, o, s, nullptr);
+    hipLaunchKernelGGL(k_write_info, dim3(1), dim3(64), 0, s, h->st, info_dev, (int32_t)h->fused,
+                       nullptr);
+    HIP_TRY(hipGetLastError());
+    return GSR_OK;
+}
+
+// The precision form, stream-ordered: all max_refine correction steps are enqueued; the
+// test of each step runs on the device and, once it stops the loop, gates the launches of
+// the remaining steps (their residual, inner solve and update return at once).
+gsr_status f32v_solve_async(gsr_handle* h, const double* b, double* x, const gsr_solve_opts& o,
+                            gsr_solve_info* info_dev, hipStream_t s) {
+    const Geo& g = h->g;
+    const int32_t* gate = ref_stop_flag(h);
+    hipLaunchKernelGGL(k_ref_begin, dim3(1), dim3(64), 0, s, h->ref);
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(g.m, kBlock, kVecBlocksMax)), dim3(kBlock), 0, s,
+                       h->rows(), b, h->r);
+    fill(x, g.n, 0.0, s);
+    for (int k = 0; k < o.max_refine; ++k) {
+        fwd_enqueue<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx,
+                           inner_opts(o, k), s, gate);
+        ref_step(h, x, o, s);
+        if (k + 1 < o.max_refine)
+            launch_aprod1<double, A1_RESID>(h, h->vals, x, h->r, b, s, gate);
+    }
+    hipLaunchKernelGGL(k_write_info, dim3(1), dim3(64), 0, s, h->st, info_dev, (int32_t)h->fused,
+                       h->ref);
     HIP_TRY(hipGetLastError());
     return GSR_OK;
 }
@@ -613,24 +738,26 @@ gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_
                        gsr_solve_info* info, hipStream_t s) {
     const Geo& g = h->g;
     LsqrWork& w = h->trans;
-    GSR_TRY(ensure_work(w, g.n, g.m));
+    GSR_TRY(ensure_work(w, g.n, h->rows()));
     GSR_TRY(capture_graph(h, w, [&](hipStream_t cs) { trans_iteration(h, w, cs); }));
     // beta_1 u_1 = D g
     hipLaunchKernelGGL(k_copy_norm<true>, dim3(h->Gn), dim3(kBlock), 0, s, g.n, gvec, h->p64,
                        w.u, h->xt, h->partA);
     hipLaunchKernelGGL(k_scal_init1, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->Gn,
                        o.itnlim, o.fixed_iters, o.atol, o.btol, o.conlim);
-    fill(w.w, g.m, 0.0, s);
-    fill(w.z, g.m, 0.0, s);
+    fill(w.w, h->rows(), 0.0, s);
+    fill(w.z, h->rows(), 0.0, s);
     // alpha_1 v_1 = A D u_1 (and, fused, s = A^T v~_1 for the first u-step)
     if (h->fused) {
         fill(h->s, g.n, 0.0, s);
         launch_fused<double, true>(h, h->vals, h->attT64, w.v, h->s, h->partB, s, nullptr, w.w,
                                    w.z);
-        hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB, h->G12);
+        hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partB,
+                           h->G12 + h->nc1);
     } else {
         launch_aprod1<double, A1_LSQR_T>(h, h->vals, h->xt, w.v, nullptr, s);
-        hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partA, h->G1);
+        hipLaunchKernelGGL(k_scal_init2, dim3(1), dim3(kBlock), 0, s, h->st, h->partA,
+                           h->G1 + h->nc1);
     }
     ProfileOut prof;
     if (o.profile)
@@ -639,10 +766,140 @@ gsr_status trans_solve(gsr_handle* h, const double* gvec, double* mu, const gsr_
             &prof.ms1, &prof.ms2, &prof.n));
     else
         GSR_TRY(run_iterations(h, w, o, s));
-    hipLaunchKernelGGL(k_final<false>, dim3(h->Gm), dim3(kBlock), 0, s, g.m, nullptr, w.z, w.w,
+    hipLaunchKernelGGL(k_final<false>, dim3(h->Gm), dim3(kBlock), 0, s, h->rows(), nullptr, w.z, w.w,
                        w.v, mu, h->st);
     HIP_TRY(hipGetLastError());
     return read_info(h, info, s, prof);
+}
+
+void release_constraints(gsr_handle* h) {
+    dfree(h->crow);
+    dfree(h->cacc);
+    dfree(h->cu_col);
+    dfree(h->cu_ptr);
+    dfree(h->cu_row);
+    dfree(h->cu_val);
+    h->crow = h->cu_row = nullptr;
+    h->cacc = h->cu_val = nullptr;
+    h->cu_col = h->cu_ptr = nullptr;
+    h->cptr = h->ccol = nullptr;
+    h->cval = nullptr;
+    h->n_con = h->nnz_c = h->ncu = 0;
+    h->nc1 = 0;
+}
+
+// Library-side arrays of the constraint rows: the row of every entry, and a copy of the
+// entries grouped by column (radix sort by column, run-length encoding into the distinct
+// columns, offsets by a scan).  Synchronizes.
+gsr_status build_constraints(gsr_handle* h, int64_t n_con, int64_t nnz, const int64_t* ptr,
+                             const int64_t* col, const double* val, hipStream_t s) {
+    if (n_con == 0) return GSR_OK;
+    h->n_con = n_con;
+    h->nnz_c = nnz;
+    h->cptr = ptr;
+    h->ccol = col;
+    h->cval = val;
+    h->nc1 = 1;
+    GSR_TRY(dalloc(&h->cacc, n_con));
+    fill(h->cacc, n_con, 0.0, s);
+    {  // row pointer non-decreasing
+        int* d_flags = nullptr;
+        GSR_TRY(dalloc(&d_flags, 1));
+        int flags = 0;
+        hipError_t e = hipMemsetAsync(d_flags, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_con_check_ptr, dim3(grid_for(n_con, kBlock, kVecBlocksMax)),
+                               dim3(kBlock), 0, s, n_con, ptr, d_flags);
+            e = hipMemcpyAsync(&flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dfree(d_flags);
+        if (e != hipSuccess) return hip_fail(e, "constraint rows");
+        if (flags) return fail(GSR_E_LAYOUT, "constraint ptr decreases");
+    }
+    if (nnz == 0) return GSR_OK;
+    h->Gcon = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nnz + 4095) / 4096));
+    h->con_per_block = (nnz + h->Gcon - 1) / h->Gcon;
+    GSR_TRY(dalloc(&h->crow, nnz));
+    GSR_TRY(dalloc(&h->cu_row, nnz));
+    GSR_TRY(dalloc(&h->cu_val, nnz));
+    GSR_TRY(dalloc(&h->cu_col, nnz));
+    int32_t *seq = nullptr, *perm = nullptr, *counts = nullptr;
+    int64_t* ksorted = nullptr;
+    int* d_misc = nullptr;  // [0] check flags, [1] number of distinct columns
+    void* temp = nullptr;
+    gsr_status rc = GSR_OK;
+    auto cleanup = [&]() {
+        dfree(seq);
+        dfree(perm);
+        dfree(counts);
+        dfree(ksorted);
+        dfree(d_misc);
+        dfree(temp);
+    };
+    if ((rc = dalloc(&seq, nnz)) != GSR_OK || (rc = dalloc(&perm, nnz)) != GSR_OK ||
+        (rc = dalloc(&counts, nnz + 1)) != GSR_OK || (rc = dalloc(&ksorted, nnz)) != GSR_OK ||
+        (rc = dalloc(&d_misc, 2)) != GSR_OK) {
+        cleanup();
+        return rc;
+    }
+    int misc[2] = {0, 0};
+    hipError_t e = hipMemsetAsync(d_misc, 0, 2 * sizeof(int), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_con_rows, dim3(grid_for(nnz, kBlock, kVecBlocksMax)), dim3(kBlock),
+                           0, s, n_con, nnz, h->g.n, ptr, col, h->crow, seq, d_misc);
+        e = hipMemcpyAsync(misc, d_misc, sizeof(int), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "constraint rows");
+    }
+    if (misc[0]) {
+        cleanup();
+        return fail(GSR_E_LAYOUT, "constraint column out of [0, n_cols)");
+    }
+    int end_bit = 1;
+    while (end_bit < 63 && (1LL << end_bit) <= h->g.n) ++end_bit;
+    const int n = (int)nnz;
+    size_t b1 = 0, b2 = 0, b3 = 0;
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, b1, col, ksorted, seq, perm, n, 0, end_bit, s);
+    if (e == hipSuccess)
+        e = hipcub::DeviceRunLengthEncode::Encode(nullptr, b2, ksorted, h->cu_col, counts,
+                                                  d_misc + 1, n, s);
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::ExclusiveSum(nullptr, b3, counts, counts, n + 1, s);
+    if (e == hipSuccess) e = hipMalloc(&temp, std::max(std::max(b1, b2), std::max<size_t>(b3, 1)));
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(temp, b1, col, ksorted, seq, perm, n, 0, end_bit,
+                                               s);
+    if (e == hipSuccess)
+        e = hipcub::DeviceRunLengthEncode::Encode(temp, b2, ksorted, h->cu_col, counts, d_misc + 1,
+                                                  n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&misc[1], d_misc + 1, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "constraint columns");
+    }
+    h->ncu = misc[1];
+    // offsets of the column groups: exclusive scan of the counts with a zero appended
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, counts + h->ncu, (int64_t)1, 0);
+    rc = dalloc(&h->cu_ptr, h->ncu + 1);
+    int32_t* offs = seq;  // seq is no longer needed: the offsets as int32 (nnz < 2^31)
+    if (rc == GSR_OK) {
+        e = hipcub::DeviceScan::ExclusiveSum(temp, b3, counts, offs, (int)h->ncu + 1, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_widen_i32, dim3(grid_for(h->ncu + 1, kBlock, kVecBlocksMax)),
+                               dim3(kBlock), 0, s, h->ncu + 1, offs, h->cu_ptr);
+            hipLaunchKernelGGL(k_con_gather, dim3(grid_for(nnz, kBlock, kVecBlocksMax)),
+                               dim3(kBlock), 0, s, nnz, perm, h->crow, val, h->cu_row, h->cu_val);
+            e = hipStreamSynchronize(s);
+        }
+        if (e != hipSuccess) rc = hip_fail(e, "constraint columns");
+    }
+    cleanup();
+    return rc;
 }
 
 gsr_solve_opts default_opts() {
@@ -663,6 +920,7 @@ gsr_status check_opts(const gsr_solve_opts& o) {
     if (!(o.atol >= 0) || !(o.btol >= 0)) return fail(GSR_E_INVAL, "atol/btol must be >= 0");
     if (!(o.conlim >= 0)) return fail(GSR_E_INVAL, "conlim must be >= 0");
     if (o.refine_itnlim < 0) return fail(GSR_E_INVAL, "refine_itnlim < 0");
+    if (!(o.refine_first_tol >= 0)) return fail(GSR_E_INVAL, "refine_first_tol must be >= 0");
     if (o.precision != GSR_F64 && o.precision != GSR_F32V)
         return fail(GSR_E_INVAL, "unknown precision %d", o.precision);
     if (o.precision == GSR_F32V && o.max_refine < 1) return fail(GSR_E_INVAL, "max_refine < 1");
@@ -787,7 +1045,8 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
     if ((st = dalloc(&h->p64, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->s, g.n)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->xt, g.n)) != GSR_OK) return bail(st);
-    const int part_len = std::max(std::max(std::max(h->G1, h->Gm), h->Gn), h->G12);
+    // one more slot than the largest grid: the constraint rows' partial sum
+    const int part_len = std::max(std::max(std::max(h->G1, h->Gm), h->Gn), h->G12) + 1;
     if ((st = dalloc(&h->partA, part_len)) != GSR_OK) return bail(st);
     if ((st = dalloc(&h->partB, 4 * (size_t)part_len)) != GSR_OK) return bail(st);
     if (h->lds2 && (st = dalloc(&h->part_ig, (size_t)std::max(h->G2s, h->G12) * (g.I + 1))) !=
@@ -830,6 +1089,7 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
     unsigned long long n_empty = 0;
     if ((st = colnorm<double>(h, vals, h->attT64, h->p64, s, &n_empty)) != GSR_OK)
         return bail(st);
+    h->allow_empty = so.allow_empty_cols;
     if (n_empty && !so.allow_empty_cols)
         return bail(fail(GSR_E_LAYOUT, "%llu all-zero column(s); set allow_empty_cols", n_empty));
     if (h->fused && g.m > 0) {
@@ -864,6 +1124,14 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         unsigned long long n_empty32 = 0;
         if ((st = colnorm<float>(h, h->vals32, h->attT32, h->p32, s, &n_empty32)) != GSR_OK)
             return bail(st);
+        // the precision form's workspaces, so that its stream-ordered solve allocates nothing
+        if ((st = ensure_work(h->fwd32, g.m, g.n)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->dx, g.n)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->r, g.m)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->ref_part, 2 * (size_t)h->Gn)) != GSR_OK) return bail(st);
+        if ((st = dalloc(&h->ref, 1)) != GSR_OK) return bail(st);
+        hipError_t e = hipHostMalloc((void**)&h->ref_host, sizeof(RefState), hipHostMallocDefault);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
     }
     *out = h;
     return GSR_OK;
@@ -896,6 +1164,8 @@ gsr_status gsr_destroy(gsr_handle* h) {
     dfree(h->dx);
     dfree(h->r);
     dfree(h->ref_part);
+    dfree(h->ref);
+    release_constraints(h);
     if (h->ref_host) (void)hipHostFree(h->ref_host);
     if (h->st_host) (void)hipHostFree(h->st_host);
     if (h->cap) (void)hipStreamDestroy(h->cap);
@@ -905,9 +1175,101 @@ gsr_status gsr_destroy(gsr_handle* h) {
 
 gsr_status gsr_get_size(const gsr_handle* h, int64_t* n_rows, int64_t* n_cols) {
     if (!h) return fail(GSR_E_INVAL, "handle is NULL");
-    if (n_rows) *n_rows = h->g.m;
+    if (n_rows) *n_rows = h->rows();
     if (n_cols) *n_cols = h->g.n;
     return GSR_OK;
+}
+
+gsr_status gsr_update_values(gsr_handle* h, const double* vals, void* stream) {
+    g_last_error.clear();
+    if (!h) return fail(GSR_E_INVAL, "handle is NULL");
+    const Geo& g = h->g;
+    if (g.m > 0 && !vals) return fail(GSR_E_INVAL, "vals is NULL");
+    if ((uintptr_t)vals & 15) return fail(GSR_E_INVAL, "vals must be 16-byte aligned");
+    GSR_TRY(set_device(h));
+    hipStream_t s = as_stream(stream);
+    // the captured iterations of the unfused path read the coefficients from `vals`
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamSynchronize(h->cap));
+    for (LsqrWork* w : {&h->fwd64, &h->fwd64v, &h->fwd32, &h->trans}) {
+        if (w->graph) (void)hipGraphExecDestroy(w->graph);
+        w->graph = nullptr;
+    }
+    h->vals = vals;
+    if (g.m > 0) {
+        const int64_t ntiles_att = (g.m + kStepRows - 1) / kStepRows;
+        const int64_t natt = ntiles_att * kTileAtt;
+        hipLaunchKernelGGL(k_gather_att<double>, dim3(grid_for(natt, kBlock, 8192)), dim3(kBlock),
+                           0, s, g.m, ntiles_att, vals, h->rowT, h->attT64);
+        const int64_t nv = h->ntiles * kTileVals;
+        if (h->tiles64)
+            hipLaunchKernelGGL(k_make_tiles<double>, dim3(grid_for(nv, kBlock, 8192)),
+                               dim3(kBlock), 0, s, g.m, h->ntiles, vals, h->tiles64);
+        if (h->tiles32)
+            hipLaunchKernelGGL(k_make_tiles<float>, dim3(grid_for(nv, kBlock, 8192)),
+                               dim3(kBlock), 0, s, g.m, h->ntiles, vals, h->tiles32);
+        if (h->vals32) {
+            const int64_t nnz = g.m * kPar;
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nnz, kBlock, 8192)), dim3(kBlock), 0, s,
+                               nnz, vals, h->vals32);
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(natt, kBlock, 8192)), dim3(kBlock), 0, s,
+                               natt, h->attT64, h->attT32);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    unsigned long long n_empty = 0, n_empty32 = 0;
+    GSR_TRY(colnorm<double>(h, vals, h->attT64, h->p64, s, &n_empty));
+    if (h->vals32) GSR_TRY(colnorm<float>(h, h->vals32, h->attT32, h->p32, s, &n_empty32));
+    if (n_empty && !h->allow_empty)
+        return fail(GSR_E_LAYOUT, "%llu all-zero column(s) in the new values; set "
+                                  "allow_empty_cols at setup", n_empty);
+    return GSR_OK;
+}
+
+gsr_status gsr_set_constraints(gsr_handle* h, int64_t n_con, const int64_t* ptr,
+                               const int64_t* col, const double* val, void* stream) {
+    g_last_error.clear();
+    if (!h) return fail(GSR_E_INVAL, "handle is NULL");
+    if (n_con < 0) return fail(GSR_E_INVAL, "n_con < 0");
+    if (n_con > (int64_t)INT32_MAX) return fail(GSR_E_UNSUPPORTED, "more than 2^31-1 constraint rows");
+    if (n_con > 0 && !ptr) return fail(GSR_E_INVAL, "ptr is NULL");
+    GSR_TRY(set_device(h));
+    hipStream_t s = as_stream(stream);
+    int64_t ends[2] = {0, 0};
+    if (n_con > 0) {
+        HIP_TRY(hipMemcpyAsync(&ends[0], ptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&ends[1], ptr + n_con, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ends[0] != 0) return fail(GSR_E_LAYOUT, "constraint ptr[0] must be 0");
+        if (ends[1] < 0) return fail(GSR_E_LAYOUT, "constraint ptr[n_con] < 0");
+        if (ends[1] > (int64_t)INT32_MAX)
+            return fail(GSR_E_UNSUPPORTED, "more than 2^31-1 constraint coefficients");
+        if (ends[1] > 0 && (!col || !val)) return fail(GSR_E_INVAL, "col or val is NULL");
+    }
+    // every solve's state depends on the number of rows: drop it (graphs included)
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamSynchronize(h->cap));
+    free_work(h->fwd64);
+    free_work(h->fwd64v);
+    free_work(h->fwd32);
+    free_work(h->trans);
+    release_constraints(h);
+    gsr_status rc = build_constraints(h, n_con, ends[1], ptr, col, val, s);
+    if (rc != GSR_OK) release_constraints(h);
+    // the preconditioner includes the constraint rows (binary64 coefficients in both
+    // precisions); the workspaces of the stream-ordered solves are allocated again here
+    unsigned long long n_empty = 0;
+    gsr_status rc2 = colnorm<double>(h, h->vals, h->attT64, h->p64, s, &n_empty);
+    if (rc2 == GSR_OK && h->vals32)
+        rc2 = colnorm<float>(h, h->vals32, h->attT32, h->p32, s, &n_empty);
+    if (rc2 == GSR_OK) rc2 = ensure_work(h->fwd64, h->rows(), h->g.n);
+    if (rc2 == GSR_OK && h->vals32) {
+        dfree(h->r);
+        h->r = nullptr;
+        rc2 = dalloc(&h->r, h->rows());
+        if (rc2 == GSR_OK) rc2 = ensure_work(h->fwd32, h->rows(), h->g.n);
+    }
+    return rc != GSR_OK ? rc : rc2;
 }
 
 gsr_status gsr_aprod1(gsr_handle* h, const double* x, double* y, void* stream) {
@@ -977,50 +1339,24 @@ gsr_status gsr_lsqr_solve(gsr_handle* h, const double* b, double* x, const gsr_s
     // binary32 coefficients inside, binary64 residual correction outside
     if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
     const Geo& g = h->g;
-    if (!h->dx) GSR_TRY(dalloc(&h->dx, g.n));
-    if (!h->r) GSR_TRY(dalloc(&h->r, g.m));
-    HIP_TRY(hipMemcpyAsync(h->r, b, sizeof(double) * g.m, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_ref_begin, dim3(1), dim3(64), 0, s, h->ref);
+    HIP_TRY(hipMemcpyAsync(h->r, b, sizeof(double) * h->rows(), hipMemcpyDeviceToDevice, s));
     fill(x, g.n, 0.0, s);
-    if (!h->ref_part) GSR_TRY(dalloc(&h->ref_part, 2 * (size_t)h->Gn));
-    if (!h->ref_host)
-        HIP_TRY(hipHostMalloc((void**)&h->ref_host, 2 * sizeof(double) * h->Gn,
-                              hipHostMallocDefault));
-    int total_itn = 0, k = 0;
     gsr_solve_info inner = {};
-    double* part = h->ref_part;
-    double* hp = h->ref_host;
-    double sums[2] = {0, 0};
-    hipError_t e = hipSuccess;
-    gsr_status rc = GSR_OK;
-    while (k < o.max_refine) {
-        gsr_solve_opts ok = o;
-        if (k > 0 && o.refine_itnlim > 0) ok.itnlim = o.refine_itnlim;
-        rc = fwd_solve<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx, ok, &inner,
-                              s);
-        if (rc != GSR_OK) break;
-        total_itn += inner.itn;
-        ++k;
-        hipLaunchKernelGGL(k_axpy_norms, dim3(h->Gn), dim3(kBlock), 0, s, g.n, h->dx, x, part);
-        e = hipMemcpyAsync(hp, part, 2 * sizeof(double) * h->Gn, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "refinement norms");
-            break;
-        }
-        sums[0] = sums[1] = 0.0;
-        for (int q = 0; q < h->Gn; ++q) {
-            sums[0] += hp[q];
-            sums[1] += hp[h->Gn + q];
-        }
-        if (std::sqrt(sums[0]) <= o.refine_tol * std::sqrt(sums[1])) break;
-        if (k < o.max_refine)
-            launch_aprod1<double, A1_RESID>(h, h->vals, x, h->r, b, s);
+    for (int k = 0; k < o.max_refine; ++k) {
+        GSR_TRY(fwd_solve<float>(h, h->fwd32, h->vals32, h->attT32, h->p32, h->r, h->dx,
+                                 inner_opts(o, k), &inner, s));
+        ref_step(h, x, o, s);
+        HIP_TRY(hipMemcpyAsync(h->ref_host, h->ref, sizeof(RefState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h->ref_host->stop) break;
+        launch_aprod1<double, A1_RESID>(h, h->vals, x, h->r, b, s);
     }
-    if (rc != GSR_OK) return rc;
+    HIP_TRY(hipGetLastError());
     if (info) {
         *info = inner;
-        info->itn = total_itn;
-        info->n_refine = k;
+        info->itn = h->ref_host->itn;
+        info->n_refine = h->ref_host->n_refine;
     }
     return GSR_OK;
 }
@@ -1045,11 +1381,11 @@ gsr_status gsr_lsqr_solve_async(gsr_handle* h, const double* b, double* x,
     if (!h || !x || !info_dev || (!b && h->g.m > 0)) return fail(GSR_E_INVAL, "null argument");
     const gsr_solve_opts o = opts ? *opts : default_opts();
     GSR_TRY(check_opts(o));
-    if (o.precision != GSR_F64)
-        return fail(GSR_E_UNSUPPORTED, "the stream-ordered solve is binary64 only");
     if (o.profile) return fail(GSR_E_INVAL, "profile needs host synchronization");
     GSR_TRY(set_device(h));
-    return fwd_solve_async(h, b, x, o, info_dev, as_stream(stream));
+    if (o.precision == GSR_F64) return fwd_solve_async(h, b, x, o, info_dev, as_stream(stream));
+    if (!h->vals32) return fail(GSR_E_UNSUPPORTED, "binary32 copy not built (build_f32 = 0)");
+    return f32v_solve_async(h, b, x, o, info_dev, as_stream(stream));
 }
 
 gsr_status gsr_lsqr_solve_adjoint(gsr_handle* h, const double* gvec, double* mu, double* lam,

@@ -54,6 +54,15 @@ struct LsqrState {
     int32_t itn, itnlim, fixed, istop, stop, pending, pend_b, nonfinite;
 };
 
+// State of the residual-correction loop of the precision form, in device memory: once
+// `stop` is set, the launches of later correction steps return at once.
+struct RefState {
+    int32_t stop;       // no further correction step
+    int32_t n_refine;   // outer steps taken
+    int32_t itn;        // inner iterations summed over the steps taken
+    int32_t nonfinite;  // a non-finite value stopped an inner solve
+};
+
 // ---------------------------------------------------------------------------------------
 // small helpers
 
@@ -493,11 +502,15 @@ __device__ __forceinline__ void scal_alpha(LsqrState* st, double vv, double zz, 
     if (st->itn >= st->itnlim) st->stop = 1;
 }
 
+// gate (may be NULL): when *gate is set the solve is not started (st keeps the stopped state
+// of the previous solve, so all its launches return at once).
 static __global__ __launch_bounds__(kBlock) void k_scal_init1(LsqrState* st, const double* part,
                                                               int G, int32_t itnlim, int32_t fixed,
                                                               double atol, double btol,
-                                                              double conlim) {
+                                                              double conlim,
+                                                              const int32_t* gate = nullptr) {
     __shared__ double sh[kBlock / kWave];
+    if (gate && *gate) return;
     const double ss = reduce_partials(part, G, sh);
     if (threadIdx.x == 0) scal_init1(st, ss, itnlim, fixed, atol, btol, conlim);
 }
@@ -536,11 +549,13 @@ static __global__ void k_to_f32(int64_t n, const double* __restrict__ src, float
         dst[j] = (float)src[j];  // round to nearest even
 }
 
-// x += d; partials (2 rows of G): sum d^2, sum x^2
+// x += d; partials (2 rows of G): sum d^2, sum x^2.  Nothing once the loop has stopped.
 static __global__ __launch_bounds__(kBlock) void k_axpy_norms(int64_t n, const double* __restrict__ d,
                                                        double* __restrict__ x,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials,
+                                                       const RefState* __restrict__ ref) {
     __shared__ double sh[kBlock / kWave];
+    if (ref->stop) return;
     double add = 0.0, axx = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
@@ -554,6 +569,41 @@ static __global__ __launch_bounds__(kBlock) void k_axpy_norms(int64_t n, const d
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
     tot = block_sum<kBlock>(axx, sh);
     if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = tot;
+}
+
+static __global__ void k_ref_begin(RefState* ref) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ref = RefState{0, 0, 0, 0};
+}
+
+// After correction step k (x += d_k done by k_axpy_norms): count the step and its inner
+// iterations; the loop ends when ||d_k|| <= tol ||x||, after max_refine steps, or when the
+// inner solve met a non-finite value.
+static __global__ __launch_bounds__(kBlock) void k_ref_check(RefState* __restrict__ ref,
+                                                             const LsqrState* __restrict__ st,
+                                                             const double* __restrict__ part,
+                                                             int G, double tol,
+                                                             int32_t max_refine) {
+    __shared__ double sh[kBlock / kWave];
+    if (ref->stop) return;
+    const double dd = reduce_partials(part, G, sh);
+    const double xx = reduce_partials(part + G, G, sh);
+    if (threadIdx.x != 0) return;
+    RefState r = *ref;
+    r.itn += st->itn;
+    r.n_refine += 1;
+    if (st->nonfinite) {
+        r.nonfinite = 1;
+        r.stop = 1;
+    } else if (sqrt(dd) <= tol * sqrt(xx) || r.n_refine >= max_refine) {
+        r.stop = 1;
+    }
+    *ref = r;
+}
+
+static __global__ void k_copy(int64_t n, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+        dst[j] = src[j];
 }
 
 // dvals[i, k] = r_i lam_c - mu_i x_c  on the stored pattern.

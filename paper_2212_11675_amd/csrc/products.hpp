@@ -268,7 +268,8 @@ __device__ __forceinline__ void run_close(double (&acc)[NV], int32_t& ckey, F&& 
 //   A1_RESID : y[i] = b[i] - sum_i
 // LSQR modes also write the block partial of sum y[i]^2.  LDSI: the instrumental part of xx
 // is staged in LDS (dynamic LDS of n_instr doubles).  TILED: coefficients and indices come
-// from the row tiles (vals, star, att, instr then unused).
+// from the row tiles (vals, star, att, instr then unused).  gate (may be NULL): nothing is
+// done when *gate is set (a residual of a correction step that will not be taken).
 enum { A1_ADD = 0, A1_LSQR = 1, A1_LSQR_T = 2, A1_RESID = 3 };
 
 template <typename VT, int MODE, bool TILED, bool LDSI>
@@ -277,9 +278,11 @@ static __global__ __launch_bounds__(512) void k_aprod1(
     const int32_t* __restrict__ att, const int32_t* __restrict__ instr,
     const VT* __restrict__ tiles, const double* __restrict__ xx, double* __restrict__ y,
     const double* __restrict__ b,
-    const LsqrState* __restrict__ st, double* __restrict__ partials, int chunk_rows) {
+    const LsqrState* __restrict__ st, double* __restrict__ partials, int chunk_rows,
+    const int32_t* __restrict__ gate) {
     extern __shared__ double lxi[];
     __shared__ double sh[512 / kWave];
+    if (gate && *gate) return;
     constexpr bool kLsqr = (MODE == A1_LSQR || MODE == A1_LSQR_T);
     double xs = 1.0, ys = 0.0;
     if (kLsqr) {
@@ -504,7 +507,8 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 // TRANS: the same pass for the transposed operator D A^T (the adjoint solve), where the
 // row-space vector is v~:  v~[r] = su (A xt)[r] - beta sv v~[r]  (xt = p o u~), preceded on
 // the same rows by the pending update z += f1 w; w = sv v~ - f2 w of the row-space z, w.
-// Partials then are 4 rows of gridDim: sum v~^2, sum z^2, sum z w, sum w^2.
+// Partials then are 4 rows (pstride apart; entries past gridDim belong to the constraint
+// rows): sum v~^2, sum z^2, sum z w, sum w^2.
 //
 // INIT: the initial aprod 2 of a solve: u~ is left as it is (no dot products) and only
 // s += A^T u~ is scattered (star-ordered columns; the attitude pass follows as usual).
@@ -513,7 +517,7 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     Geo g, const VT* __restrict__ tiles, const int32_t* __restrict__ star,
     const double* __restrict__ xx, double* __restrict__ uu, double* __restrict__ s,
     const LsqrState* __restrict__ st, double* __restrict__ partials,
-    double* __restrict__ part, int chunk_rows, double* __restrict__ ww_vec = nullptr,
+    double* __restrict__ part, int chunk_rows, int pstride, double* __restrict__ ww_vec = nullptr,
     double* __restrict__ zz_vec = nullptr) {
     extern __shared__ double lds[];  // [n_instr + 1] sums, then [n_instr] staged xt
     __shared__ double sh[1024 / kWave];
@@ -632,7 +636,7 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
     const double tot = block_sum<1024>(usq, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
     if (TRANS) {
-        const int G = gridDim.x;
+        const int G = pstride;
         double t2 = block_sum<1024>(zsq, sh);
         if (threadIdx.x == 0) partials[G + blockIdx.x] = t2;
         t2 = block_sum<1024>(zw, sh);

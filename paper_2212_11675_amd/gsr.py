@@ -14,7 +14,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsr.so")
-ABI_VERSION = 3  # GSR_ABI_VERSION of include/gsr.h
+ABI_VERSION = 4  # GSR_ABI_VERSION of include/gsr.h
 
 GSR_F64 = 0
 GSR_F32V = 1
@@ -28,7 +28,8 @@ EXPORTS = (
     "gsr_abi_version", "gsr_status_string", "gsr_last_error", "gsr_lsqr_setup", "gsr_destroy",
     "gsr_get_size", "gsr_aprod1", "gsr_aprod2", "gsr_aprod1_f32v", "gsr_aprod2_f32v",
     "gsr_precond", "gsr_residual", "gsr_lsqr_solve", "gsr_lsqr_solve_var",
-    "gsr_lsqr_solve_async", "gsr_lsqr_solve_adjoint", "gsr_grad_vals",
+    "gsr_lsqr_solve_async", "gsr_lsqr_solve_adjoint", "gsr_grad_vals", "gsr_set_constraints",
+    "gsr_update_values",
     "gsr_batch_setup", "gsr_batch_destroy", "gsr_batch_col_offsets", "gsr_batch_aprod1",
     "gsr_batch_aprod2", "gsr_batch_solve",
 )
@@ -57,7 +58,8 @@ class SolveOpts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("conlim", ctypes.c_double),
-                ("refine_itnlim", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("refine_itnlim", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("refine_first_tol", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -109,6 +111,8 @@ def load() -> ctypes.CDLL:
         "gsr_lsqr_solve_adjoint": (st, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                         ctypes.POINTER(SolveInfo), vp]),
         "gsr_grad_vals": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "gsr_set_constraints": (st, [vp, i64, vp, vp, vp, vp]),
+        "gsr_update_values": (st, [vp, vp, vp]),
         "gsr_batch_setup": (st, [i32, ctypes.POINTER(Dims), ctypes.POINTER(i64), vp, vp, vp, vp,
                                  i32, ctypes.POINTER(SetupOpts), vp, ctypes.POINTER(vp)]),
         "gsr_batch_destroy": (st, [vp]),
@@ -159,10 +163,11 @@ def make_dims(n_rows, n_stars, n_dfa, n_instr, n_glob=1) -> Dims:
 
 def solve_opts(itnlim=100, fixed_iters=True, atol=1e-14, btol=1e-14, precision=GSR_F64,
                max_refine=4, refine_tol=1e-10, check_every=16, profile=False,
-               conlim=0.0, refine_itnlim=0) -> SolveOpts:
+               conlim=0.0, refine_itnlim=0, refine_first_tol=0.0) -> SolveOpts:
     return SolveOpts(int(itnlim), int(bool(fixed_iters)), float(atol), float(btol),
                      int(precision), int(max_refine), float(refine_tol), int(check_every),
-                     int(bool(profile)), float(conlim), int(refine_itnlim), 0)
+                     int(bool(profile)), float(conlim), int(refine_itnlim), 0,
+                     float(refine_first_tol))
 
 
 class Handle:
@@ -172,8 +177,13 @@ class Handle:
         self.ptr = ptr
         self.dims = dims
         self._keep = keep
+        self._con = None
+        self.n_obs = int(dims.n_rows)
+        self._sizes()
+
+    def _sizes(self):
         n_rows, n_cols = ctypes.c_int64(), ctypes.c_int64()
-        _check(load().gsr_get_size(ptr, ctypes.byref(n_rows), ctypes.byref(n_cols)),
+        _check(load().gsr_get_size(self.ptr, ctypes.byref(n_rows), ctypes.byref(n_cols)),
                "gsr_get_size")
         self.m, self.n = n_rows.value, n_cols.value
 
@@ -275,8 +285,9 @@ def read_solve_info(buf: torch.Tensor) -> dict:
 
 def gsr_lsqr_solve_async(h: Handle, b, x, info_dev, opts: SolveOpts | None = None,
                          stream=None) -> None:
-    """Stream-ordered binary64 PC-LSQR: no synchronization, capturable into a graph; the
-    solve information lands in info_dev (see solve_info_buffer / read_solve_info)."""
+    """Stream-ordered PC-LSQR (binary64, or the precision form with its correction loop
+    tested on the device): no synchronization, capturable into a graph; the solve
+    information lands in info_dev (see solve_info_buffer / read_solve_info)."""
     _check(load().gsr_lsqr_solve_async(h.ptr, _dev(b, torch.float64, h.m, "b"),
                                        _dev(x, torch.float64, h.n, "x"),
                                        ctypes.byref(opts) if opts is not None else None,
@@ -301,8 +312,42 @@ def gsr_grad_vals(h: Handle, r, mu, x, lam, dvals, stream=None):
                                 _dev(mu, torch.float64, h.m, "mu"),
                                 _dev(x, torch.float64, h.n, "x"),
                                 _dev(lam, torch.float64, h.n, "lam"),
-                                _dev(dvals, torch.float64, 24 * h.m, "dvals"),
+                                _dev(dvals, torch.float64, 24 * h.n_obs, "dvals"),
                                 _stream(stream)), "gsr_grad_vals")
+
+
+def gsr_update_values(h: Handle, vals, stream=None):
+    """New coefficient values (same index map): the handle's copies and preconditioner are
+    rebuilt in place; the handle references `vals` from now on."""
+    _check(load().gsr_update_values(h.ptr, _dev(vals, torch.float64, 24 * h.n_obs, "vals"),
+                                    _stream(stream)), "gsr_update_values")
+    h._keep = (vals,) + tuple(h._keep[1:])
+
+
+def gsr_set_constraints(h: Handle, ptr=None, col=None, val=None, stream=None):
+    """Constraint rows C (compressed rows: ptr [n_con+1] int64, col [nnz] int64 absolute
+    columns, val [nnz] float64, CUDA tensors) below the observation rows; None removes them.
+    Row-space vectors of the handle then have h.m = n_rows + n_con entries."""
+    if ptr is None:
+        _check(load().gsr_set_constraints(h.ptr, 0, None, None, None, _stream(stream)),
+               "gsr_set_constraints")
+        h._con = None
+    else:
+        n_con = ptr.numel() - 1
+        if n_con < 0:
+            raise ValueError("ptr: at least one entry (n_con + 1) is required")
+        nnz = col.numel()
+        args = (_dev(ptr, torch.int64, n_con + 1, "ptr"), _dev(col, torch.int64, nnz, "col"),
+                _dev(val, torch.float64, nnz, "val"))
+        h._con = None  # after an error the handle has no constraint rows
+        try:
+            _check(load().gsr_set_constraints(h.ptr, n_con, *args, _stream(stream)),
+                   "gsr_set_constraints")
+            h._con = (ptr, col, val)
+        finally:
+            h._sizes()
+        return
+    h._sizes()
 
 
 # ---- batching -----------------------------------------------------------------------------
@@ -364,9 +409,17 @@ def gsr_batch_aprod2(b: Batch, Y, X, stream=None):
 
 
 def gsr_batch_solve(b: Batch, B, X, opts: SolveOpts | None = None, stream=None) -> list[dict]:
+    """Per-pair solve information (entry s*k + j).  On a breakdown (GSR_E_BREAKDOWN) the
+    raised GsrError carries the same list as `.info`."""
     info = (SolveInfo * (b.n_sys * b.k))()
-    _check(load().gsr_batch_solve(b.ptr, _dev(B, torch.float64, b.m * b.k, "B"),
-                                  _dev(X, torch.float64, b.n * b.k, "X"),
-                                  ctypes.byref(opts) if opts is not None else None, info,
-                                  _stream(stream)), "gsr_batch_solve")
-    return [i.as_dict() for i in info]
+    st = load().gsr_batch_solve(b.ptr, _dev(B, torch.float64, b.m * b.k, "B"),
+                                _dev(X, torch.float64, b.n * b.k, "X"),
+                                ctypes.byref(opts) if opts is not None else None, info,
+                                _stream(stream))
+    out = [i.as_dict() for i in info]
+    try:
+        _check(st, "gsr_batch_solve")
+    except GsrError as e:
+        e.info = out
+        raise
+    return out

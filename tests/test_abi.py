@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = gsr.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.gsr_abi_version() == 3
+    assert lib.gsr_abi_version() == gsr.ABI_VERSION == 4
     assert lib.gsr_status_string(0) == b"ok"
     assert lib.gsr_status_string(-2) == b"matrix layout violated"
 

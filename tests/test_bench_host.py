@@ -46,16 +46,21 @@ def test_counter_summary_scaling_and_staleness(tmp_path, monkeypatch):
     gib_kib = (1 << 30) / 1024
     copy = "__amd_rocclr_copyBuffer(void*, void*)"
     kern = "void gsr::k_aprod12<double, 1, false, false>(gsr::Geo, ...)"
+    init = "void gsr::k_aprod12<double, 1, false, true>(gsr::Geo, ...)"  # a solve's first pass
     # FETCH reads half of the copy's true bytes, WRITE all of them
     _write_counters(tmp_path / "f", "FETCH_SIZE",
-                    [(copy, gib_kib / 2)] * 3 + [(copy, 5.0), (kern, 3e6), (kern, 3e6)])
+                    [(copy, gib_kib / 2)] * 3 + [(copy, 5.0), (init, 1e6), (kern, 3e6),
+                                                 (kern, 3e6)])
     _write_counters(tmp_path / "w", "WRITE_SIZE",
-                    [(copy, gib_kib)] * 3 + [(kern, 1e5), (kern, 1e5)])
+                    [(copy, gib_kib)] * 3 + [(init, 7.0), (kern, 1e5), (kern, 1e5)])
     monkeypatch.setattr(bench, "traffic_path",
                         lambda k, wl: str(tmp_path / f"{k}_{wl}_hbm_traffic.txt"))
-    out = bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), "k_aprod12", "wl", "cmd")
+    out = bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"),
+                            "k_aprod12<double, 1, false, false>", "wl", "cmd")
+    assert out.endswith("k_aprod12_wl_hbm_traffic.txt")
     text = open(out).read()
     assert "fetch_scale: 2.0000" in text and "write_scale: 1.0000" in text
+    assert "dispatches_fetch: 2" in text  # the initial pass is not averaged in
     traffic = 3e6 * 1024 * 2 + 1e5 * 1024
     got = bench.stored_traffic("k_aprod12", "wl", algorithmic=traffic * 0.99)
     assert got == pytest.approx(traffic, rel=1e-6)

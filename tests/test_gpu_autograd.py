@@ -102,3 +102,59 @@ def test_gradcheck_tiny():
     # device atomics reorder the column sums: repeated backward passes agree to rounding only
     assert torch.autograd.gradcheck(lambda v, bb: gad.lstsq(v, bb, st), (vals, b), eps=1e-6,
                                     atol=1e-6, rtol=1e-5, nondet_tol=1e-12)
+
+
+def test_one_handle_reused_in_training_loop():
+    """The structure's handle is set up once; coefficients changed in place between steps
+    (as by an optimizer) are brought into it with gsr_update_values.  Every step's gradients
+    match those of a fresh structure on the same values, device memory stays flat over the
+    steps, and a backward pass run after another solve changed the values gets its own."""
+    shape = synth.Shape(400, 10, 60, 60, 50, seed=95, name="loop")
+    sysd = synth.system(shape)
+    S = oracle_system(sysd)
+    dev = torch.device("cuda:0")
+    b = torch.from_numpy(S.aprod1(synth.x_true(shape)) + synth.noise(shape)).to(dev)
+    xr = torch.from_numpy(synth.x_ref(shape)).to(dev)
+    t, st = _structure(sysd, shape)
+    vals = t["vals"].clone().requires_grad_(True)
+    rng = np.random.default_rng(96)
+    free, ptr0 = [], None
+    for step in range(6):
+        x = gad.lstsq(vals, b, st, atol=1e-14, btol=1e-14)
+        loss = ((x - xr) ** 2).sum()
+        loss.backward()
+        if ptr0 is None:
+            ptr0 = st._handle.ptr.value
+        assert st._handle.ptr.value == ptr0  # no new handle
+        # the same step on a fresh structure
+        t2, st2 = _structure(sysd, shape)
+        v2 = vals.detach().clone().requires_grad_(True)
+        x2 = gad.lstsq(v2, b, st2, atol=1e-14, btol=1e-14)
+        ((x2 - xr) ** 2).sum().backward()
+        assert rel(host(x.detach()), host(x2.detach())) <= 1e-12, step
+        assert rel(host(vals.grad), host(v2.grad)) <= 1e-10, step
+        st2.close()
+        del t2, st2, v2, x2
+        with torch.no_grad():  # an optimizer-like step in place
+            vals.add_(torch.from_numpy(1e-3 * rng.standard_normal(vals.numel())).to(dev))
+            vals.grad = None
+        torch.cuda.synchronize()
+        free.append(torch.cuda.mem_get_info()[0])
+    print(f"[loop] free device memory over the steps (MiB): {[f >> 20 for f in free]}")
+    assert max(free[1:]) - min(free[1:]) <= 64 << 20
+    # two solves on different values, then the first one's backward
+    va = vals.detach().clone().requires_grad_(True)
+    vb = (vals.detach() * 1.01).requires_grad_(True)
+    xa = gad.lstsq(va, b, st, atol=1e-14, btol=1e-14)
+    xb = gad.lstsq(vb, b, st, atol=1e-14, btol=1e-14)
+    ((xa - xr) ** 2).sum().backward()
+    ((xb - xr) ** 2).sum().backward()
+    for v, xv in ((va, xa), (vb, xb)):
+        t3, st3 = _structure(sysd, shape)
+        v3 = v.detach().clone().requires_grad_(True)
+        x3 = gad.lstsq(v3, b, st3, atol=1e-14, btol=1e-14)
+        ((x3 - xr) ** 2).sum().backward()
+        assert rel(host(xv.detach()), host(x3.detach())) <= 1e-12
+        assert rel(host(v.grad), host(v3.grad)) <= 1e-10
+        st3.close()
+    st.close()

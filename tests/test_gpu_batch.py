@@ -134,6 +134,44 @@ def test_batched_converged_solve():
     b.close()
 
 
+def test_batched_nonfinite_pair_is_reported():
+    """A non-finite right-hand side in one (system, rhs) pair: the call reports a breakdown,
+    the solve information names that pair, and every other pair still matches the oracle."""
+    k, iters = 4, 9
+    print(f"[batch nonfinite] k={k} iters={iters}", flush=True)
+    b, systems, _ = make_batch(SHAPES, k)
+    B = np.zeros((b.m, k))
+    oracles = []
+    for s, sysd in enumerate(systems):
+        S = oracle_system(sysd)
+        r0, r1 = b.row_offset[s], b.row_offset[s + 1]
+        for j in range(k):
+            B[r0:r1, j] = S.aprod1(synth.rhs_x(SHAPES[s], j)) + synth.rhs_noise(SHAPES[s], j,
+                                                                               S.m)
+        oracles.append(S)
+    bad_s, bad_j = 3, 2
+    B[b.row_offset[bad_s] + 5, bad_j] = np.nan
+    Xd = torch.empty(b.n * k, dtype=torch.float64, device="cuda")
+    with pytest.raises(gsr.GsrError) as ei:
+        gsr.gsr_batch_solve(b, cuda(B.ravel()), Xd, gsr.solve_opts(itnlim=iters, fixed_iters=True))
+    assert ei.value.status == -5
+    infos = ei.value.info
+    Xg = host(Xd).reshape(b.n, k)
+    for s, S in enumerate(oracles):
+        r0, r1 = b.row_offset[s], b.row_offset[s + 1]
+        c0, c1 = b.col_offset[s], b.col_offset[s + 1]
+        for j in range(k):
+            f = infos[s * k + j]
+            if (s, j) == (bad_s, bad_j):
+                assert f["nonfinite"] == 1
+                continue
+            assert f["nonfinite"] == 0 and f["fused"] == 1, (s, j)
+            xo, io = S.lsqr(B[r0:r1, j], itnlim=iters, fixed=True)
+            assert f["itn"] == io["itn"], (s, j)
+            assert rel(Xg[c0:c1, j], xo) <= 1e-10, (s, j)
+    b.close()
+
+
 def test_batched_condition_limit_stops_every_pair():
     """conlim: each (system, right-hand side) pair stops on its own condition estimate at the
     step the oracle's solo solve does."""

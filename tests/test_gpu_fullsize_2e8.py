@@ -1,11 +1,13 @@
 """The 2e8-row workload (5e6 stars x 40 observations, 1e5 attitude knots per axis, 1e4
-instrumental columns: the largest LDS footprint of the fused row pass) at its real size,
-set up as the benchmark sets it up.  The CPU oracle cannot take the whole system, so:
-  - aprod 1 on 2,000 sampled rows, computed by the oracle on the sub-system of those rows;
-  - the adjoint identity <A x, y> = <x, A^T y>;
-  - the first PC-LSQR iterate against its closed form, the minimizer of ||A D z - b|| along
-    z = D A^T b (LSQR's first step), built from the library's products;
-  - LSQR's residual estimate against the directly computed residual after 5 iterations.
+instrumental columns: the largest LDS footprint of the fused row pass, more than 2^31
+coefficients) at its real size, set up as the benchmark sets it up, against the oracle on
+the whole system held in host memory (45 GB):
+  - aprod 1, aprod 2 and the preconditioner, every entry;
+  - the binary32 products, every entry, against the oracle on the binary32-rounded
+    coefficients (row chunks of the system, so that only one rounded chunk is in memory);
+  - the first two PC-LSQR iterates and their residual estimate;
+  - the adjoint identity and the residual estimate after 5 iterations against the oracle's
+    residual.
 """
 import numpy as np
 import pytest
@@ -13,65 +15,95 @@ import torch
 
 import oracle
 import synth
-from gpu_util import assert_close_scaled, host, rel, upload_chunked
+from gpu_util import assert_close_scaled, cuda, host, open_system, oracle_system, rel
 from paper_2212_11675_amd import gsr
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+SHAPE = synth.S5M_O40
 
 
-def test_full_size_2e8_sampled_rows_adjoint_and_first_iterate():
-    shape = synth.S5M_O40
-    print(f"[2e8] {shape.name}: generating and uploading", flush=True)
-    t, d, rp = upload_chunked(shape)
-    m, n = d["n_rows"], shape.n_cols
-    h = gsr.gsr_lsqr_setup(gsr.make_dims(m, d["n_stars"], d["n_dfa"], d["n_instr"]), t["vals"],
-                           t["star"], t["att"], t["instr"])
-    dev = torch.device("cuda:0")
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(2208)
-    # aprod 1 on sampled rows
-    x = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
-    y = torch.zeros(m, dtype=torch.float64, device=dev)
-    gsr.gsr_aprod1(h, x, y)
-    rows = np.sort(np.random.default_rng(2209).choice(m, size=2000, replace=False))
-    parts = [synth.rows(shape, int(r), int(r) + 1, row_ptr=rp) for r in rows]
-    sub = {k: np.concatenate([p[k] for p in parts]) for k in ("vals", "star", "att", "instr")}
-    S = oracle.System(dict(n_rows=len(rows), n_stars=d["n_stars"], n_dfa=d["n_dfa"],
-                           n_instr=d["n_instr"], n_glob=1),
-                      sub["vals"], sub["star"], sub["att"], sub["instr"])
-    print("[2e8] sampled rows vs oracle", flush=True)
-    assert_close_scaled(host(y)[rows], S.aprod1(host(x)), 1e-13)
-    # adjoint identity
-    yr = torch.randn(m, dtype=torch.float64, device=dev, generator=gen)
-    xs = torch.zeros(n, dtype=torch.float64, device=dev)
-    gsr.gsr_aprod2(h, yr, xs)
-    lhs, rhs = float(torch.dot(y, yr)), float(torch.dot(x, xs))
-    scale = float(torch.linalg.norm(y) * torch.linalg.norm(yr))
-    print(f"[2e8] <Ax,y> {lhs:.12e} <x,A^T y> {rhs:.12e}", flush=True)
-    assert abs(lhs - rhs) <= 1e-12 * scale
-    # right-hand side b = A x_true + e (library product, noise from the generator)
-    b = torch.from_numpy(synth.noise(shape)).to(dev)
-    gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
-    # first iterate: x1 = tau D^2 A^T b with tau = <A D g, b> / ||A D g||^2, g = D A^T b
-    p = torch.empty(n, dtype=torch.float64, device=dev)
-    gsr.gsr_precond(h, p)
-    s = torch.zeros(n, dtype=torch.float64, device=dev)
-    gsr.gsr_aprod2(h, b, s)
-    g = p * s
-    w = torch.zeros(m, dtype=torch.float64, device=dev)
-    gsr.gsr_aprod1(h, p * g, w)
-    tau = float(torch.dot(w, b) / torch.dot(w, w))
-    x1 = torch.empty(n, dtype=torch.float64, device=dev)
-    info = gsr.gsr_lsqr_solve(h, b, x1, gsr.solve_opts(itnlim=1, fixed_iters=True))
-    assert info["fused"] == 1
-    print("[2e8] first iterate vs closed form", flush=True)
-    assert rel(host(x1), host(tau * p * g)) <= 1e-12
-    # residual estimate after 5 iterations
-    x5 = torch.empty(n, dtype=torch.float64, device=dev)
-    info = gsr.gsr_lsqr_solve(h, b, x5, gsr.solve_opts(itnlim=5, fixed_iters=True))
-    r = torch.empty(m, dtype=torch.float64, device=dev)
-    gsr.gsr_residual(h, b, x5, r)
-    rn = float(torch.linalg.norm(r))
-    print(f"[2e8] rnorm estimate {info['rnorm']:.12e} direct {rn:.12e}", flush=True)
-    assert abs(info["rnorm"] - rn) <= 1e-10 * rn
+@pytest.fixture(scope="module")
+def big():
+    print(f"[2e8] {SHAPE.name}: generating on the host", flush=True)
+    sysd = synth.system(SHAPE)
+    S = oracle_system(sysd)
+    print("[2e8] uploading and setting up", flush=True)
+    h, t = open_system(sysd, build_f32=True)
+    yield dict(sysd=sysd, S=S, h=h, t=t)
     h.close()
+
+
+def test_2e8_products_and_preconditioner_vs_oracle(big):
+    S, h = big["S"], big["h"]
+    rng = np.random.default_rng(2208)
+    x = rng.standard_normal(S.n)
+    yd = torch.zeros(S.m, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod1(h, cuda(x), yd)
+    print("[2e8] aprod1 vs oracle", flush=True)
+    y = host(yd)
+    assert_close_scaled(y, S.aprod1(x), 1e-13)
+    yr = rng.standard_normal(S.m)
+    xd = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod2(h, cuda(yr), xd)
+    print("[2e8] aprod2 vs oracle", flush=True)
+    xs = host(xd)
+    assert_close_scaled(xs, S.aprod2(yr), 1e-12)
+    # adjoint identity of the library's own products
+    lhs, rhs = float(np.dot(y, yr)), float(np.dot(x, xs))
+    assert abs(lhs - rhs) <= 1e-12 * float(np.linalg.norm(y) * np.linalg.norm(yr))
+    p = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_precond(h, p)
+    print("[2e8] preconditioner vs oracle", flush=True)
+    np.testing.assert_allclose(host(p), S.colnorm(), rtol=1e-12, atol=0)
+
+
+def test_2e8_binary32_products_vs_oracle(big):
+    sysd, S, h = big["sysd"], big["S"], big["h"]
+    rng = np.random.default_rng(2210)
+    x = rng.standard_normal(S.n)
+    yr = rng.standard_normal(S.m)
+    yd = torch.zeros(S.m, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod1_f32v(h, cuda(x), yd)
+    xd = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod2_f32v(h, cuda(yr), xd)
+    y32, x32 = host(yd), host(xd)
+    d = sysd["dims"]
+    rp = sysd["row_ptr"]
+    xo = np.zeros(S.n)
+    step = 500_000  # stars per chunk (2e7 rows)
+    for s0 in range(0, d["n_stars"], step):
+        r0, r1 = int(rp[s0]), int(rp[min(s0 + step, d["n_stars"])])
+        print(f"[2e8] binary32 rows {r0}..{r1}", flush=True)
+        lo = sysd["vals"][24 * r0: 24 * r1].astype(np.float32).astype(np.float64)
+        C = oracle.System(dict(d, n_rows=r1 - r0), lo, sysd["star"][r0:r1], sysd["att"][r0:r1],
+                          sysd["instr"][6 * r0: 6 * r1])
+        assert_close_scaled(y32[r0:r1], C.aprod1(x), 1e-13)
+        xo = C.aprod2(yr[r0:r1], xo)
+    assert_close_scaled(x32, xo, 1e-12)
+
+
+def test_2e8_first_iterations_and_residual_vs_oracle(big):
+    S, h = big["S"], big["h"]
+    b = S.aprod1(synth.x_true(SHAPE)) + synth.noise(SHAPE)
+    p = S.colnorm()
+    bd = cuda(b)
+    for k in (1, 2):
+        xg = torch.empty(S.n, dtype=torch.float64, device="cuda")
+        info = gsr.gsr_lsqr_solve(h, bd, xg, gsr.solve_opts(itnlim=k, fixed_iters=True))
+        assert info["fused"] == 1
+        print(f"[2e8] PC-LSQR {k} vs oracle", flush=True)
+        xo, io = S.lsqr(b, itnlim=k, fixed=True, p=p)
+        assert rel(host(xg), xo) <= 1e-10, k
+        for key in ("rnorm", "arnorm", "anorm", "znorm"):
+            assert abs(info[key] - io[key]) <= 1e-10 * abs(io[key]), (k, key)
+    # residual estimate after 5 iterations against the oracle's residual of the GPU iterate
+    x5 = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    info = gsr.gsr_lsqr_solve(h, bd, x5, gsr.solve_opts(itnlim=5, fixed_iters=True))
+    r = S.residual(b, host(x5))
+    rn = float(np.linalg.norm(r))
+    rg = torch.empty(S.m, dtype=torch.float64, device="cuda")
+    gsr.gsr_residual(h, bd, x5, rg)
+    print(f"[2e8] rnorm estimate {info['rnorm']:.12e} oracle residual {rn:.12e}", flush=True)
+    assert abs(info["rnorm"] - rn) <= 1e-10 * rn
+    assert_close_scaled(host(rg), r, 1e-12)

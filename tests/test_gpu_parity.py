@@ -317,7 +317,8 @@ def test_variance_estimate_vs_oracle(cfg_small, k):
     # there only says both sides accumulate the same estimate
     v = host(var)
     assert (v >= 0).all()
-    tol = 1e-10 if k <= 40 else 1e-2
+    tol = 1e-10 if k <= 40 else 1e-3
+    print(f"[var] k={k} max rel diff {np.max(np.abs(v - vo) / vo):.3e}", flush=True)
     np.testing.assert_allclose(v, vo, rtol=tol, atol=0)
     if k == 100:
         v40 = torch.empty_like(var)
@@ -393,6 +394,11 @@ def test_stopping_rules_vs_oracle(noise, atol, btol, conlim):
     slack = 2 if (atol, btol, conlim) == (0.0, 0.0, 0.0) else 0
     assert abs(info["itn"] - io["itn"]) <= slack
     assert rel(host(x), xo) <= (1e-10 if info["itn"] == io["itn"] else 1e-8)
+    # the condition estimate grows with every step: against the oracle's after the GPU's
+    # number of steps (the machine-precision tests may stop a step apart: device atomics
+    # change the rounding of the compared quantities)
+    if info["itn"] != io["itn"]:
+        _, io = S.lsqr(b, itnlim=info["itn"], fixed=True)
     assert abs(info["acond"] - io["acond"]) <= 1e-3 * io["acond"]
     h.close()
 
@@ -445,3 +451,196 @@ def test_stream_ordered_solve_and_graph_capture(cfg_small):
         assert rel(host(xg), host(xe)) <= 1e-12, rep
         xo, _ = S.lsqr(bnew, itnlim=fg["itn"], fixed=True)
         assert rel(host(xg), xo) <= 1e-10, rep
+
+
+def test_precision_form_loose_first_solve(cfg_small):
+    """refine_first_tol: the first binary32 inner solve stops at a loose tolerance, the
+    correction solves at the final one; against the oracle's refinement with the same
+    settings and the binary64 solution."""
+    c = cfg_small
+    S = c["S"]
+    lo = c["sysd"]["vals"].astype(np.float32)
+    x64o, _ = S.lsqr(c["b"], itnlim=400, fixed=False, atol=1e-15, btol=1e-15)
+    x = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    o = gsr.solve_opts(itnlim=300, fixed_iters=False, atol=1e-12, btol=1e-12,
+                       precision=gsr.GSR_F32V, max_refine=4, refine_tol=1e-10,
+                       refine_first_tol=1e-4)
+    info = gsr.gsr_lsqr_solve(c["h"], cuda(c["b"]), x, o)
+    xro, outer, inner = S.refine(c["b"], lo, max_outer=4, refine_tol=1e-10, inner_itnlim=300,
+                                 inner_atol=1e-12, inner_btol=1e-12, first_tol=1e-4)
+    print(f"[first tol] GPU {info['n_refine']} steps {info['itn']} its; oracle {outer} {inner}")
+    assert info["n_refine"] == outer
+    # the stop iteration of a tolerance test may move by a step or two with rounding
+    assert abs(info["itn"] - sum(inner)) <= 2 * outer
+    assert rel(host(x), xro) <= 1e-8
+    assert rel(host(x), x64o) <= 1e-8
+
+
+def test_stream_ordered_precision_form_and_graph_capture(cfg_small):
+    """gsr_lsqr_solve_async with GSR_F32V: the correction loop's test taken on the device.
+    Against the synchronous precision form (fixed schedule, and tolerances with the loop
+    ending before max_refine so that the remaining launches must do nothing), the oracle's
+    refinement, and captured into a graph replayed on new right-hand sides."""
+    c = cfg_small
+    S, h = c["S"], c["h"]
+    lo = c["sysd"]["vals"].astype(np.float32)
+    info = gsr.solve_info_buffer()
+    xs = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(xs)
+    # fixed schedule: 30 + 6 steps
+    o2 = gsr.solve_opts(itnlim=30, fixed_iters=True, precision=gsr.GSR_F32V, max_refine=2,
+                        refine_tol=0.0, refine_itnlim=6)
+    gsr.gsr_lsqr_solve(h, cuda(c["b"]), xs, o2)
+    gsr.gsr_lsqr_solve_async(h, cuda(c["b"]), x, info, o2)
+    f = gsr.read_solve_info(info)
+    assert (f["itn"], f["n_refine"], f["nonfinite"]) == (36, 2, 0)
+    assert rel(host(x), host(xs)) <= 1e-12
+    xso, _, _ = S.refine(c["b"], lo, max_outer=2, refine_tol=0.0, inner_itnlim=30,
+                         later_itnlim=6, inner_fixed=True)
+    assert rel(host(x), xso) <= 1e-10
+    # tolerances: the loop stops after fewer than max_refine steps
+    o = gsr.solve_opts(itnlim=200, fixed_iters=False, atol=1e-12, btol=1e-12,
+                       precision=gsr.GSR_F32V, max_refine=5, refine_tol=1e-10,
+                       refine_first_tol=1e-4)
+    ref = gsr.gsr_lsqr_solve(h, cuda(c["b"]), xs, o)
+    assert ref["n_refine"] < 5
+    x.fill_(7.0)
+    gsr.gsr_lsqr_solve_async(h, cuda(c["b"]), x, info, o)
+    f = gsr.read_solve_info(info)
+    assert (f["itn"], f["n_refine"], f["istop"]) == (ref["itn"], ref["n_refine"], ref["istop"])
+    assert rel(host(x), host(xs)) <= 1e-12
+    # zero right-hand side: one step, no iteration, x = 0
+    gsr.gsr_lsqr_solve_async(h, torch.zeros(S.m, dtype=torch.float64, device="cuda"), x, info,
+                             o)
+    f0 = gsr.read_solve_info(info)
+    assert (f0["itn"], f0["n_refine"], f0["istop"]) == (0, 1, 4)
+    assert float(x.abs().max()) == 0.0
+    # captured into a graph, replayed on new right-hand sides with eager work in between
+    bg = cuda(c["b"])
+    xg = torch.empty_like(xs)
+    infog = gsr.solve_info_buffer()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gsr.gsr_lsqr_solve_async(h, bg, xg, infog, o)
+    rng = np.random.default_rng(43)
+    for rep in range(3):
+        print(f"[f32v graph] replay {rep}", flush=True)
+        bnew = S.aprod1(rng.standard_normal(S.n)) + 1e-3 * rng.standard_normal(S.m)
+        bg.copy_(cuda(bnew))
+        g.replay()
+        torch.cuda.synchronize()
+        fg = gsr.read_solve_info(infog)
+        xe = torch.empty_like(xs)
+        ie = gsr.gsr_lsqr_solve(h, cuda(bnew), xe, o)
+        assert (fg["itn"], fg["n_refine"]) == (ie["itn"], ie["n_refine"]), rep
+        assert rel(host(xg), host(xe)) <= 1e-12, rep
+        xo, outer, _ = S.refine(bnew, lo, max_outer=5, refine_tol=1e-10, inner_itnlim=200,
+                                inner_atol=1e-12, inner_btol=1e-12, first_tol=1e-4)
+        assert rel(host(xg), xo) <= 1e-8, rep
+
+
+def _edge_system(shape, seed):
+    """A generated system with what the generator never emits: instrumental indices in
+    random order within every row, repeated instrumental indices in every fifth row, and two
+    stars (the first and one in the middle) with no rows at all."""
+    sysd = synth.system(shape)
+    rng = np.random.default_rng(seed)
+    m = sysd["dims"]["n_rows"]
+    ins = sysd["instr"].reshape(m, 6).copy()
+    for i in range(m):
+        ins[i] = ins[i][rng.permutation(6)]
+    ins[::5, 3] = ins[::5, 0]  # a repeated column in those rows
+    ins[1::7, 5] = ins[1::7, 2]
+    keep = (sysd["star"] != 0) & (sysd["star"] != shape.n_stars // 2)
+    out = dict(sysd)
+    out["instr"] = np.ascontiguousarray(ins[keep].ravel())
+    out["star"] = np.ascontiguousarray(sysd["star"][keep])
+    out["att"] = np.ascontiguousarray(sysd["att"][keep])
+    out["vals"] = np.ascontiguousarray(sysd["vals"].reshape(m, 24)[keep].ravel())
+    out["dims"] = dict(sysd["dims"], n_rows=int(keep.sum()))
+    return out
+
+
+@pytest.mark.parametrize("shape", [synth.Shape(300, 10, 60, 40, 50, seed=131, name="fused"),
+                                   synth.Shape(300, 10, 60, 40, 10500, seed=132,
+                                               name="unfused_instr10500")],
+                         ids=lambda s: s.name)
+def test_unsorted_repeated_instrumental_and_empty_stars(shape):
+    """Inputs the interface accepts but the generator never produces: instrumental indices
+    out of order and repeated within a row, stars with no observation (empty astrometric
+    columns).  Products, preconditioner, binary32 products and 5 PC-LSQR iterations against
+    the oracle on the same arrays."""
+    print(f"[edge] {shape.name}", flush=True)
+    sysd = _edge_system(shape, seed=shape.seed)
+    S = oracle_system(sysd)
+    h, _ = open_system(sysd, allow_empty_cols=True, build_f32=True)
+    rng = np.random.default_rng(shape.seed + 1)
+    x, y0 = rng.standard_normal(S.n), rng.standard_normal(S.m)
+    yd = cuda(y0)
+    gsr.gsr_aprod1(h, cuda(x), yd)
+    assert_close_scaled(host(yd), S.aprod1(x, y0), 1e-13)
+    y, x0 = rng.standard_normal(S.m), rng.standard_normal(S.n)
+    xd = cuda(x0)
+    gsr.gsr_aprod2(h, cuda(y), xd)
+    assert_close_scaled(host(xd), S.aprod2(y, x0), 1e-13)
+    p = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_precond(h, p)
+    po = S.colnorm()
+    assert (po[:5] == 0).all() and np.array_equal(host(p) == 0, po == 0)
+    np.testing.assert_allclose(host(p), po, rtol=1e-12, atol=0)
+    S32 = S.with_vals(sysd["vals"].astype(np.float32).astype(np.float64))
+    yd = cuda(y0)
+    gsr.gsr_aprod1_f32v(h, cuda(x), yd)
+    assert_close_scaled(host(yd), S32.aprod1(x, y0), 1e-13)
+    xd = cuda(x0)
+    gsr.gsr_aprod2_f32v(h, cuda(y), xd)
+    assert_close_scaled(host(xd), S32.aprod2(y, x0), 1e-13)
+    b = S.aprod1(synth.x_true(shape)[: S.n]) + synth.noise(shape, S.m)
+    xg = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    info = gsr.gsr_lsqr_solve(h, cuda(b), xg, gsr.solve_opts(itnlim=5, fixed_iters=True))
+    assert info["fused"] == int(shape.n_instr <= 10240)
+    xo, io = S.lsqr(b, itnlim=5, fixed=True)
+    assert info["itn"] == io["itn"] == 5
+    assert rel(host(xg), xo) <= 1e-10
+    assert (host(xg)[:5] == 0).all()
+    h.close()
+
+
+def test_full_size_binary32_products_and_refinement_vs_oracle():
+    """The 2e7-row system at its real size with binary32-stored coefficients: the binary32
+    products and preconditioner against the oracle on the binary32-rounded coefficients, and
+    a two-step fixed correction schedule against the oracle's refinement."""
+    shape = synth.S1M_O20
+    print(f"[full f32] {shape.name}: generating", flush=True)
+    sysd = synth.system(shape)
+    S = oracle_system(sysd)
+    lo = sysd["vals"].astype(np.float32)
+    S32 = S.with_vals(lo.astype(np.float64))
+    h, _ = open_system(sysd, build_f32=True)
+    rng = np.random.default_rng(63)
+    x = rng.standard_normal(S.n)
+    yd = torch.zeros(S.m, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod1_f32v(h, cuda(x), yd)
+    print("[full f32] aprod1 oracle", flush=True)
+    assert_close_scaled(host(yd), S32.aprod1(x), 1e-13)
+    y = rng.standard_normal(S.m)
+    xd = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod2_f32v(h, cuda(y), xd)
+    print("[full f32] aprod2 oracle", flush=True)
+    assert_close_scaled(host(xd), S32.aprod2(y), 1e-12)
+    p = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_precond(h, p, precision=gsr.GSR_F32V)
+    np.testing.assert_allclose(host(p), S32.colnorm(), rtol=1e-12, atol=0)
+    b = S.aprod1(synth.x_true(shape)) + synth.noise(shape)
+    xg = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    info = gsr.gsr_lsqr_solve(h, cuda(b), xg, gsr.solve_opts(
+        itnlim=3, fixed_iters=True, precision=gsr.GSR_F32V, max_refine=2, refine_tol=0.0,
+        refine_itnlim=2))
+    assert (info["itn"], info["n_refine"]) == (5, 2)
+    print("[full f32] refinement oracle", flush=True)
+    xo, outer, inner = S.refine(b, lo, max_outer=2, refine_tol=0.0, inner_itnlim=3,
+                                later_itnlim=2, inner_fixed=True)
+    assert (outer, inner) == (2, [3, 2])
+    assert rel(host(xg), xo) <= 1e-10
+    h.close()
