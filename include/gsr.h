@@ -301,6 +301,25 @@ gsr_status gsr_update_values(gsr_handle *h, const double *vals, void *stream);
 gsr_status gsr_set_constraints(gsr_handle *h, int64_t n_con, const int64_t *ptr,
                                const int64_t *col, const double *val, void *stream);
 
+/*
+ * aprod mode 2 (x += A^T y) straight on the caller's arrays, with no handle and no allocation:
+ * for callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation), who therefore cannot call gsr_lsqr_setup either.
+ * The arguments are those of gsr_lsqr_setup (dims host; vals [n_rows*24] binary64, star,
+ * att [n_rows] int32, instr [n_rows*6] int32, device, same layout and sorting) plus y
+ * [n_rows] and x [n_cols] (device; x is read and written), and the stream.  The kernels'
+ * block partial sums of the instrumental and global columns live in a fixed device array of
+ * the library (32 MiB, one per GPU the library runs on, held until the process ends); the
+ * attitude columns take one atomic add per coefficient (no attitude-ordered copy without a
+ * setup), so this is slower than gsr_aprod2.  Indices are not validated.  Every call on a GPU
+ * shares that array: calls that overlap on one GPU (several streams or threads) race.
+ * Errors: GSR_E_INVAL; GSR_E_UNSUPPORTED when n_instr exceeds 10240, the most one block's
+ * LDS sums and the fixed array allow; GSR_E_NODEVICE; GSR_E_HIP.
+ */
+gsr_status gsr_aprod2_noalloc(const gsr_dims *dims, const double *vals, const int32_t *star,
+                              const int32_t *att, const int32_t *instr, const double *y,
+                              double *x, void *stream);
+
 /* ---- batching: many independent systems, k right-hand sides each ------------------------ */
 
 typedef struct gsr_batch gsr_batch;

@@ -29,7 +29,7 @@ EXPORTS = (
     "gsr_get_size", "gsr_aprod1", "gsr_aprod2", "gsr_aprod1_f32v", "gsr_aprod2_f32v",
     "gsr_precond", "gsr_residual", "gsr_lsqr_solve", "gsr_lsqr_solve_var",
     "gsr_lsqr_solve_async", "gsr_lsqr_solve_adjoint", "gsr_grad_vals", "gsr_set_constraints",
-    "gsr_update_values",
+    "gsr_update_values", "gsr_aprod2_noalloc",
     "gsr_batch_setup", "gsr_batch_destroy", "gsr_batch_col_offsets", "gsr_batch_aprod1",
     "gsr_batch_aprod2", "gsr_batch_solve",
 )
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
         "gsr_grad_vals": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "gsr_set_constraints": (st, [vp, i64, vp, vp, vp, vp]),
         "gsr_update_values": (st, [vp, vp, vp]),
+        "gsr_aprod2_noalloc": (st, [ctypes.POINTER(Dims), vp, vp, vp, vp, vp, vp, vp]),
         "gsr_batch_setup": (st, [i32, ctypes.POINTER(Dims), ctypes.POINTER(i64), vp, vp, vp, vp,
                                  i32, ctypes.POINTER(SetupOpts), vp, ctypes.POINTER(vp)]),
         "gsr_batch_destroy": (st, [vp]),
@@ -322,6 +323,20 @@ def gsr_update_values(h: Handle, vals, stream=None):
     _check(load().gsr_update_values(h.ptr, _dev(vals, torch.float64, 24 * h.n_obs, "vals"),
                                     _stream(stream)), "gsr_update_values")
     h._keep = (vals,) + tuple(h._keep[1:])
+
+
+def gsr_aprod2_noalloc(dims: Dims, vals, star, att, instr, y, x, stream=None):
+    """x += A^T y on the caller's arrays, no handle and no allocation (the library's fixed
+    device scratch holds the block partial sums; calls overlapping on one GPU race)."""
+    m = dims.n_rows
+    n = 5 * dims.n_stars + 3 * dims.n_dfa + dims.n_instr + dims.n_glob
+    _check(load().gsr_aprod2_noalloc(ctypes.byref(dims), _dev(vals, torch.float64, 24 * m, "vals"),
+                                     _dev(star, torch.int32, m, "star"),
+                                     _dev(att, torch.int32, m, "att"),
+                                     _dev(instr, torch.int32, 6 * m, "instr"),
+                                     _dev(y, torch.float64, m, "y"),
+                                     _dev(x, torch.float64, n, "x"), _stream(stream)),
+           "gsr_aprod2_noalloc")
 
 
 def gsr_set_constraints(h: Handle, ptr=None, col=None, val=None, stream=None):
