@@ -443,6 +443,38 @@ def form_batch(args) -> dict:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     err = float(torch.linalg.norm(Xs - Xd) / torch.linalg.norm(Xd))
+    if args.batch_fixed_only:
+        bt.close()
+        return {"metric": "batched PC-LSQR: systems/s", "value": round(len(shapes) / dt, 3),
+                "unit": "systems/s", "latency_ms_per_solve": round(1e3 * dt, 3),
+                "config": {"workload": "batch64_k8_stars1e3to2e5_obs10to60",
+                           "iterations": args.iters}}
+    # each system's solution is final only when the batched call returns: the per-system
+    # latency of the batched form is the call's latency.  Beside it, the smallest, the
+    # median and the largest system solved on their own (a batch of one, same k and
+    # iterations): the latency a system would see without batching
+    solo = {}
+    order = sorted(range(len(shapes)), key=lambda i: shapes[i].n_stars)
+    for label, i in (("smallest", order[0]), ("median", order[len(order) // 2]),
+                     ("largest", order[-1])):
+        p1 = parts[i]
+        d1 = [dims[i]]
+        c1 = {key: torch.from_numpy(p1[key]).to(dev) for key in ("vals", "star", "att", "instr")}
+        b1 = gsr.gsr_batch_setup(d1, [0, p1["dims"]["n_rows"]], c1["vals"], c1["star"],
+                                 c1["att"], c1["instr"], k, allow_empty_cols=True)
+        r0, r1 = int(row_offset[i]), int(row_offset[i + 1])
+        B1 = Bd.view(M, k)[r0:r1].contiguous().reshape(-1)  # b_j = A x_j + e_j
+        X1 = torch.empty(b1.n * k, dtype=torch.float64, device=dev)
+        gsr.gsr_batch_solve(b1, B1, X1, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            gsr.gsr_batch_solve(b1, B1, X1, opts)
+        torch.cuda.synchronize()
+        solo[label] = {"stars": shapes[i].n_stars, "rows": p1["dims"]["n_rows"],
+                       "latency_ms": round(1e3 * (time.perf_counter() - t1) / args.steps, 3)}
+        b1.close()
+        del c1
     # the same batch solved to a tolerance: every pair stops on its own tests, systems whose
     # pairs have all stopped drop out of the passes
     tol = 1e-10
@@ -475,6 +507,11 @@ def form_batch(args) -> dict:
                    "rhs_per_system": k, "rows": M, "cols": bt.n,
                    "iterations": args.iters, "setup_s": round(t_setup, 3)},
         "latency_ms_per_solve": round(1e3 * dt, 3),
+        "per_system_latency_ms": {"batched_fixed": round(1e3 * dt, 3),
+                                  "batched_converged": converged["latency_ms_per_solve"],
+                                  "definition": "every system's solution is final when the "
+                                                "batched call returns",
+                                  "alone": solo},
         "pairs_per_s": round(len(shapes) * k / dt, 2),
         "solution_rel_err_vs_x_true": err,
         "converged": converged,
@@ -598,18 +635,74 @@ SECOND_WORKLOAD = "stars1e6_obs20_dfa3e4_instr6e3"
 CPU_SAMPLE_STARS = 1_000_000  # oracle sample: rows of the first 1e6 stars (4e7 rows)
 
 
+def form_constraints(args) -> dict:
+    """The binary64 solve with and without six reference-frame-like constraint rows over a
+    tenth of the stars, timed alternately on the same system (what the constraint rows add
+    to an iteration)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2212_11675_amd import gsr
+
+    shape = synth.WORKLOADS[args.workload]
+    t, d = upload_system(shape)
+    dev = torch.device("cuda:0")
+    m, n = d["n_rows"], shape.n_cols
+    h = gsr.gsr_lsqr_setup(gsr.make_dims(m, d["n_stars"], d["n_dfa"], d["n_instr"]), t["vals"],
+                           t["star"], t["att"], t["instr"])
+    con = synth.frame_constraints(shape, n_con=6, frac=0.1)
+    cd = [torch.from_numpy(np.ascontiguousarray(con[k])).to(dev) for k in ("ptr", "col", "val")]
+    b = torch.from_numpy(synth.noise(shape)).to(dev)
+    gsr.gsr_aprod1(h, torch.from_numpy(synth.x_true(shape)).to(dev), b)
+    bc = torch.cat([b, torch.zeros(6, dtype=torch.float64, device=dev)])
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    opts = gsr.solve_opts(itnlim=args.iters, fixed_iters=True)
+
+    def run(with_con):
+        gsr.gsr_set_constraints(h, *cd) if with_con else gsr.gsr_set_constraints(h)
+        gsr.gsr_lsqr_solve(h, bc if with_con else b, x, opts)  # graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gsr.gsr_lsqr_solve(h, bc if with_con else b, x, opts)
+        torch.cuda.synchronize()
+        return args.steps * args.iters / (time.perf_counter() - t0)
+
+    plain, withc = [], []
+    for _ in range(2):
+        plain.append(run(False))
+        withc.append(run(True))
+    h.close()
+    nnz = int(con["ptr"][-1])
+    return {
+        "metric": "PC-LSQR iterations per second with and without constraint rows (binary64)",
+        "value": round(max(withc), 3), "unit": "iterations/s", "n_gpus": 1,
+        "steps": args.steps, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": shape.name, "rows": m, "cols": n, "constraint_rows": 6,
+                   "constraint_coefficients": nnz, "iterations_per_step": args.iters},
+        "without_constraints_iterations_per_s": round(max(plain), 3),
+        "overhead": round(max(plain) / max(withc) - 1.0, 4),
+    }
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--iters", type=int, default=None,
+                    help="iterations per step (default 100; 200 for --form batch and var, "
+                         "the iteration limit 5000 of the converged solves for --form grad)")
     ap.add_argument("--workload", default=None,
                     help=f"default {HEADLINE_WORKLOAD} ({SECOND_WORKLOAD} for --form grad/var)")
-    ap.add_argument("--form", default="f64", choices=["f64", "batch", "grad", "var"],
+    ap.add_argument("--form", default="f64", choices=["f64", "batch", "grad", "var",
+                                                      "constraints"],
                     help="f64: the headline binary64 solve with the precision comparison; "
                          "the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-fixed-only", action="store_true",
+                    help="--form batch: only the fixed-iteration solves (for a kernel trace)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the binary32-stored + refined comparison")
     ap.add_argument("--cpu-sample-stars", type=int, default=CPU_SAMPLE_STARS)
@@ -626,7 +719,11 @@ def main() -> None:
                     help="replay the captured iteration graph instead of event-bracketed launches")
     args = ap.parse_args()
     if args.workload is None:
-        args.workload = HEADLINE_WORKLOAD if args.form in ("f64", "batch") else SECOND_WORKLOAD
+        args.workload = (HEADLINE_WORKLOAD if args.form in ("f64", "batch", "constraints")
+                         else SECOND_WORKLOAD)
+    if args.iters is None:
+        args.iters = {"f64": 100, "batch": 200, "var": 200, "grad": 5000,
+                      "constraints": 100}[args.form]
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU split of the path is a design note, not a measured configuration",
@@ -647,7 +744,8 @@ def main() -> None:
         log("copy calibration: 3 copies of 1 GiB (1073741824 B read + written each)")
         del src, dst
     if args.form != "f64":
-        fn = {"batch": form_batch, "grad": form_grad, "var": form_var}[args.form]
+        fn = {"batch": form_batch, "grad": form_grad, "var": form_var,
+              "constraints": form_constraints}[args.form]
         print(json.dumps(fn(args)), flush=True)
         return
 

@@ -214,3 +214,44 @@ def test_batched_argument_errors():
     with pytest.raises(gsr.GsrError, match="row_offset"):
         gsr.gsr_batch_setup([d], [0, sysd["dims"]["n_rows"] - 1], dev["vals"][:-24],
                             dev["star"][:-1], dev["att"][:-1], dev["instr"][:-6], 8)
+
+
+def test_batched_extreme_systems_of_the_64_system_workload():
+    """The smallest and the largest system of the 64-system workload (1,007 and 198,336 stars,
+    3.5e4 and 6.9e6 rows), at their real sizes, batched with k = 8 right-hand sides: products
+    and 5 PC-LSQR iterations of every (system, rhs) pair against the oracle's solo solve."""
+    shapes = synth.batch_shapes()
+    order = sorted(range(len(shapes)), key=lambda i: shapes[i].n_stars)
+    pick = [shapes[order[0]], shapes[order[-1]]]
+    k, iters = 8, 5
+    print(f"[batch extremes] {[(s.n_stars, s.n_rows) for s in pick]}", flush=True)
+    b, systems, _ = make_batch(pick, k)
+    rng = np.random.default_rng(97)
+    X = rng.standard_normal((b.n, k))
+    Yd = torch.zeros(b.m * k, dtype=torch.float64, device="cuda")
+    gsr.gsr_batch_aprod1(b, cuda(X.ravel()), Yd)
+    Yg = host(Yd).reshape(b.m, k)
+    B = np.zeros((b.m, k))
+    oracles = []
+    for s, sysd in enumerate(systems):
+        S = oracle_system(sysd)
+        r0, r1 = b.row_offset[s], b.row_offset[s + 1]
+        c0, c1 = b.col_offset[s], b.col_offset[s + 1]
+        for j in range(k):
+            assert_close_scaled(Yg[r0:r1, j], S.aprod1(X[c0:c1, j]), 1e-13)
+            B[r0:r1, j] = S.aprod1(synth.rhs_x(pick[s], j)) + synth.rhs_noise(pick[s], j, S.m)
+        oracles.append(S)
+    Xd = torch.empty(b.n * k, dtype=torch.float64, device="cuda")
+    infos = gsr.gsr_batch_solve(b, cuda(B.ravel()), Xd,
+                                gsr.solve_opts(itnlim=iters, fixed_iters=True))
+    Xg = host(Xd).reshape(b.n, k)
+    for s, S in enumerate(oracles):
+        r0, r1 = b.row_offset[s], b.row_offset[s + 1]
+        c0, c1 = b.col_offset[s], b.col_offset[s + 1]
+        p = S.colnorm()
+        for j in range(k):
+            print(f"[batch extremes] system {s} rhs {j}", flush=True)
+            xo, io = S.lsqr(B[r0:r1, j], itnlim=iters, fixed=True, p=p)
+            assert infos[s * k + j]["itn"] == io["itn"] == iters
+            assert rel(Xg[c0:c1, j], xo) <= 1e-10, (s, j)
+    b.close()
