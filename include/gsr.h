@@ -189,13 +189,15 @@ gsr_status gsr_aprod2_f32v(gsr_handle *h, const double *y, double *x, void *stre
  * (device).  `precision` selects the factors of the binary64 or the binary32 coefficients. */
 gsr_status gsr_precond(gsr_handle *h, int32_t precision, double *p, void *stream);
 
-/* r = b - A x with the binary64 coefficients.  b, r [n_rows]; x [n_cols]. */
+/* r = b - A x with the binary64 coefficients.  b, r [n_rows] ([n_rows + n_con] with
+ * constraint rows); x [n_cols]. */
 gsr_status gsr_residual(gsr_handle *h, const double *b, const double *x, double *r,
                         void *stream);
 
 /*
  * PC-LSQR (Section 3 flowchart; LSQR of Paige & Saunders 1982 on A D, D = diag(p),
- * x = p o z at the end).  b [n_rows], x [n_cols] output (the caller's buffer, overwritten).
+ * x = p o z at the end).  b [n_rows] ([n_rows + n_con] with constraint rows, their
+ * right-hand side last), x [n_cols] output (the caller's buffer, overwritten).
  * opts host (NULL: 100 iterations, fixed, binary64); info host, may be NULL.
  * GSR_F32V runs  x_0 = 0, r_0 = b;  d_k = PC-LSQR(A_32, r_k);  x_{k+1} = x_k + d_k;
  * r_{k+1} = b - A x_{k+1} (binary64 coefficients) until ||d_k|| <= refine_tol ||x_{k+1}||
@@ -241,7 +243,8 @@ gsr_status gsr_lsqr_solve_async(gsr_handle *h, const double *b, double *x,
 
 /*
  * Adjoint of the least-squares solve, for a loss L(x*) with g = dL/dx* [n_cols]:
- *   mu  [n_rows] = minimum-norm solution of A^T mu = g  (LSQR on D A^T, rhs D g) = dL/db,
+ *   mu  [n_rows] = minimum-norm solution of A^T mu = g  (LSQR on D A^T, rhs D g) = dL/db
+ *       ([n_rows + n_con] with constraint rows: A is then the stacked [A; C]),
  *   lam [n_cols] = argmin || A lam - mu ||               (PC-LSQR)  = (A^T A)^{-1} g.
  * opts as for gsr_lsqr_solve (binary64 only); info (host, may be NULL) receives two entries
  * (info[0] for mu, info[1] for lam).  Synchronizes `stream`.
