@@ -172,6 +172,42 @@ def test_rank_deficient_system_made_unique_on_gpu():
                              refine_tol=1e-12, inner_itnlim=5000, inner_atol=1e-14,
                              inner_btol=1e-14)
     assert rel(host(xr), xro) <= 1e-8 and rel(host(xr), xd) <= 1e-8
+    # the stream-ordered precision form on the stacked system: the same steps and result
+    xa = torch.empty_like(x)
+    infod = gsr.solve_info_buffer()
+    ref = gsr.gsr_lsqr_solve(h, cuda(bn), xr, o32)
+    gsr.gsr_lsqr_solve_async(h, cuda(bn), xa, infod, o32)
+    f = gsr.read_solve_info(infod)
+    assert (f["itn"], f["n_refine"]) == (ref["itn"], ref["n_refine"])
+    assert rel(host(xa), host(xr)) <= 1e-12
+    h.close()
+
+
+def test_constraint_rows_only():
+    """A system with no observation rows and only constraint rows: the minimum-norm solution
+    of C x ~ c over the columns C touches, as the oracle (the other columns are empty)."""
+    shape = synth.Shape(6, 10, 10, 8, 12, seed=144)
+    sysd = synth.system(shape)
+    sys0 = dict(sysd)
+    sys0["dims"] = dict(sysd["dims"], n_rows=0)
+    for key in ("vals", "star", "att", "instr"):
+        sys0[key] = sysd[key][:0]
+    con = random_con(shape.n_cols, 5, 9, seed=145, repeat=False)
+    S = oracle.System(sys0["dims"], sys0["vals"], sys0["star"], sys0["att"], sys0["instr"],
+                      con=con)
+    h, _ = open_system(sys0, allow_empty_cols=True)
+    cd = con_dev(con)
+    gsr.gsr_set_constraints(h, *cd)
+    assert h.m == 5
+    c = np.random.default_rng(146).standard_normal(5)
+    x = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    o = gsr.solve_opts(itnlim=200, fixed_iters=False, atol=1e-14, btol=1e-14)
+    gsr.gsr_lsqr_solve(h, cuda(c), x, o)
+    xo, _ = S.lsqr(c, itnlim=200, fixed=False, atol=1e-14, btol=1e-14)
+    assert rel(host(x), xo) <= 1e-10
+    y = torch.zeros(5, dtype=torch.float64, device="cuda")
+    gsr.gsr_aprod1(h, x, y)
+    assert_close_scaled(host(y), S.aprod1(host(x)), 1e-13)
     h.close()
 
 
