@@ -47,7 +47,6 @@ struct Seg {
 };
 
 constexpr int kBTile = 2048;  // columns per tile
-constexpr int kXcd = 8;       // accelerator dies; the dispatcher places block i on die i % 8
 
 // Block index renumbered so that the blocks of one die are consecutive: contiguous work
 // ranges (one or a few systems) then stay on one die and share its L2.

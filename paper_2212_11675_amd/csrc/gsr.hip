@@ -126,16 +126,20 @@ struct gsr_handle {
     double *p64 = nullptr, *p32 = nullptr;
     double* s = nullptr;       // [n] aprod 2 accumulator (kept zero between uses)
     double* xt = nullptr;      // [n] operand of the next aprod 1 (p o v)
-    // attitude coefficients in attitude-start order (built at setup)
+    // attitude coefficients in (bucket and die, row slice, attitude start) order (built at
+    // setup): row of each entry, its column offset in the bucket, group boundaries
     int32_t *rowT = nullptr, *tT = nullptr;
     double* attT64 = nullptr;
     float* attT32 = nullptr;
+    int64_t* att_seg = nullptr;   // [att_ng + 1]
+    double* att_part = nullptr;   // [att_ng][kAxes][att_lw] group sums of the attitude pass
+    int att_ng = 1, att_w = 1, att_lw = kParAxis;
     double* part_ig = nullptr;  // [G2s][n_instr + 1] block sums of the star-ordered pass
     double *partA = nullptr, *partB = nullptr;
     LsqrState* st = nullptr;   // device scalars
     LsqrState* st_host = nullptr;  // pinned mirror
-    int G1 = 1, G2s = 1, G2t = 1, Gn = 1, Gm = 1;
-    int chunk1 = 16, chunk2s = 16, chunk2t = 16;
+    int G1 = 1, G2s = 1, Gn = 1, Gm = 1;
+    int chunk1 = 16, chunk2s = 16;
     int lds1 = 0, lds2 = 0;           // instrumental columns staged / privatized in LDS
     size_t lds1_bytes = 0, lds2_bytes = 0;
     // fused row pass (aprod 1 + star-ordered part of aprod 2), used when n_instr fits LDS
@@ -224,7 +228,6 @@ void fill(double* v, int64_t n, double val, hipStream_t s) {
 
 constexpr int kBlock1 = 512;   // aprod 1
 constexpr int kBlock2s = 512;  // aprod 2, star-ordered pass
-constexpr int kBlock2t = 256;  // aprod 2, attitude pass
 
 const double* tiles_of(const gsr_handle* h, const double*) { return h->tiles64; }
 const float* tiles_of(const gsr_handle* h, const float*) { return h->tiles32; }
@@ -291,8 +294,23 @@ void launch_reduce(const gsr_handle* h, int nblocks, double* x, int check_stop, 
                        ncols, nblocks, h->part_ig, x + h->g.ins0, h->st, check_stop);
 }
 
+// x += A^T y over the attitude columns: the attitude pass over the library's copy, then the
+// sums of its groups added to x.
+template <typename VT, int MODE>
+void launch_att(const gsr_handle* h, const VT* attT, const double* y, double* x, hipStream_t s) {
+    const Geo& g = h->g;
+    if (g.m == 0) return;
+    hipLaunchKernelGGL((k_aprod2_att<VT, MODE>), dim3(h->att_ng), dim3(kBlockAtt),
+                       sizeof(double) * kAxes * h->att_lw, s, g, attT, h->rowT, h->tT,
+                       h->att_seg, h->att_lw, y, h->att_part, h->st);
+    const int64_t n = (int64_t)kAxes * g.T;
+    hipLaunchKernelGGL(k_att_reduce, dim3(grid_for(n, kBlock, kVecBlocksMax)), dim3(kBlock), 0,
+                       s, g, h->att_w, h->att_lw, h->att_part, x, h->st,
+                       (int)(MODE == A2_LSQR || MODE == A2_LSQR_T));
+}
+
 // x += A^T y: star-ordered pass (astrometric, instrumental, global), reduction of the
-// instrumental/global block sums, attitude pass over the t-ordered copy.
+// instrumental/global block sums, attitude pass over the library's copy.
 template <typename VT, int MODE>
 void launch_aprod2(const gsr_handle* h, const VT* vals, const VT* attT, const double* y,
                    double* x, hipStream_t s) {
@@ -300,8 +318,7 @@ void launch_aprod2(const gsr_handle* h, const VT* vals, const VT* attT, const do
     hipLaunchKernelGGL((k_aprod2_star<VT, MODE>), dim3(h->G2s), dim3(kBlock2s), h->lds2_bytes, s,
                        g, vals, h->star, h->instr, y, x, h->st, h->part_ig, h->chunk2s, h->lds2);
     if (h->lds2) launch_reduce(h, h->G2s, x, (int)(MODE == A2_LSQR || MODE == A2_LSQR_T), s);
-    hipLaunchKernelGGL((k_aprod2_att<VT, MODE>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
-                       h->rowT, h->tT, y, x, h->st, h->chunk2t);
+    launch_att<VT, MODE>(h, attT, y, x, s);
     launch_con_a2<MODE == A2_SQ>(h, MODE == A2_SQ ? nullptr : y + g.m, x,
                                  (int)(MODE == A2_LSQR || MODE == A2_LSQR_T), s);
 }
@@ -324,9 +341,15 @@ gsr_status colnorm(gsr_handle* h, const VT* vals, const VT* attT, double* p, hip
     return GSR_OK;
 }
 
-// Rows sorted by attitude start t (stable radix sort of (t, row)) and the attitude
-// coefficients gathered in that order: the attitude pass of aprod 2 then sees every column's
-// contributions as consecutive runs.  Synchronizes.
+// The attitude copy (see k_aprod2_att): rows sorted by (group, slice on its die, t - b W)
+// with a stable radix sort, the group boundaries, and the attitude coefficients gathered in
+// that order.  Buckets: kAttBuckets per die, fewer when T is small, more when a bucket's sums
+// would outgrow kAttLdsBytes.  Slices: 2^17 rows (1 MiB of binary64 u~, well inside a die's
+// 4 MiB L2 beside the streamed coefficients), shorter for small systems so that every die
+// gets slices.  Synchronizes.
+constexpr int kAttBuckets = 128;
+constexpr size_t kAttLdsBytes = 40 * 1024;
+
 gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
     const Geo& g = h->g;
     const int64_t m = g.m;
@@ -334,29 +357,68 @@ gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
     GSR_TRY(dalloc(&h->tT, m));
     const int64_t ntiles_att = (m + kStepRows - 1) / kStepRows;
     GSR_TRY(dalloc(&h->attT64, ntiles_att * kTileAtt));
-    if (m == 0) return GSR_OK;
     if (m > (int64_t)INT32_MAX) return fail(GSR_E_UNSUPPORTED, "more than 2^31-1 rows");
+    auto bits_for = [](int64_t v) {  // bits that hold 0 .. v
+        int b = 0;
+        while (b < 63 && (v >> b) != 0) ++b;
+        return b;
+    };
+    const int64_t T = std::max<int64_t>(g.T, 1);
+    const int64_t w_max = (int64_t)(kAttLdsBytes / (sizeof(double) * kAxes)) - (kParAxis - 1);
+    int64_t nb = std::min<int64_t>(kAttBuckets, T);
+    int64_t w = (T + nb - 1) / nb;
+    if (w > w_max) {
+        nb = (T + w_max - 1) / w_max;
+        w = (T + nb - 1) / nb;
+    }
+    if (nb * kXcd > INT32_MAX / 2) return fail(GSR_E_UNSUPPORTED, "too many attitude knots");
+    h->att_w = (int)w;
+    h->att_lw = (int)w + kParAxis - 1;
+    h->att_ng = (int)(nb * kXcd);
+    GSR_TRY(dalloc(&h->att_seg, (size_t)h->att_ng + 1));
+    GSR_TRY(dalloc(&h->att_part, (size_t)h->att_ng * kAxes * h->att_lw));
+    if (m == 0) return GSR_OK;
+    int shift = 17;
+    while (shift > 8 && (m >> shift) < 64) --shift;
+    const int sbits = bits_for(((m - 1) >> shift) / kXcd);
+    const int tbits = bits_for(w - 1);
+    const int low_bits = sbits + tbits;
+    const int end_bit = bits_for(h->att_ng - 1) + low_bits;
     int32_t* iota = nullptr;
-    GSR_TRY(dalloc(&iota, m));
-    hipLaunchKernelGGL(k_iota, dim3(grid_for(m, kBlock, kVecBlocksMax)), dim3(kBlock), 0, s, m,
-                       iota);
-    int end_bit = 1;
-    while (end_bit < 31 && (1LL << end_bit) <= (int64_t)g.T) ++end_bit;
+    uint64_t *keys = nullptr, *keys_out = nullptr;
+    gsr_status st = dalloc(&iota, m);
+    if (st == GSR_OK) st = dalloc(&keys, m);
+    if (st == GSR_OK) st = dalloc(&keys_out, m);
+    if (st != GSR_OK) {
+        dfree(iota);
+        dfree(keys);
+        return st;
+    }
+    const dim3 vgrid(grid_for(m, kBlock, kVecBlocksMax));
+    hipLaunchKernelGGL(k_iota, vgrid, dim3(kBlock), 0, s, m, iota);
+    hipLaunchKernelGGL(k_att_keys, vgrid, dim3(kBlock), 0, s, m, shift, (int)w, sbits, tbits,
+                       h->att, keys);
     size_t temp_bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, h->att, h->tT, iota,
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys, keys_out, iota,
                                                       h->rowT, (int)m, 0, end_bit, s);
     void* temp = nullptr;
     if (e == hipSuccess) e = hipMalloc(&temp, std::max<size_t>(temp_bytes, 1));
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, h->att, h->tT, iota, h->rowT,
+        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_out, iota, h->rowT,
                                                (int)m, 0, end_bit, s);
     if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_att_seg, dim3((h->att_ng + 1 + 255) / 256), dim3(256), 0, s, m,
+                           h->att_ng, low_bits, keys_out, h->att_seg);
+        hipLaunchKernelGGL(k_att_tl, vgrid, dim3(kBlock), 0, s, m, (1ull << tbits) - 1, keys_out,
+                           h->tT);
         const int64_t total = ntiles_att * kTileAtt;
         hipLaunchKernelGGL(k_gather_att<double>, dim3(grid_for(total, kBlock, 8192)),
                            dim3(kBlock), 0, s, m, ntiles_att, h->vals, h->rowT, h->attT64);
         e = hipStreamSynchronize(s);
     }
     dfree(temp);
+    dfree(keys_out);
+    dfree(keys);
     dfree(iota);
     if (e != hipSuccess) return hip_fail(e, "attitude ordering");
     return GSR_OK;
@@ -398,8 +460,7 @@ void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u
     if (ev) mark(TRANS ? ev->a2_end : ev->a1_end, s);
     if (ev) mark(TRANS ? ev->a1_begin : ev->a2_begin, s);
     launch_reduce(h, h->G12, s_acc, 1, s);
-    hipLaunchKernelGGL((k_aprod2_att<VT, A2_LSQR>), dim3(h->G2t), dim3(kBlock2t), 0, s, g, attT,
-                       h->rowT, h->tT, u, s_acc, h->st, h->chunk2t);
+    launch_att<VT, A2_LSQR>(h, attT, u, s_acc, s);
     launch_con_a2<false>(h, u + g.m, s_acc, 1, s);
     if (ev) mark(TRANS ? ev->a1_end : ev->a2_end, s);
 }
@@ -1024,13 +1085,10 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         };
         const int o1 = occ((const void*)k_aprod1<double, A1_LSQR, false, true>, kBlock1, h->lds1_bytes);
         const int o2s = occ((const void*)k_aprod2_star<double, A2_LSQR>, kBlock2s, h->lds2_bytes);
-        const int o2t = occ((const void*)k_aprod2_att<double, A2_LSQR>, kBlock2t, 0);
         h->chunk1 = chunk_for(o1 * n_cu * kBlock1 / kWave);
         h->chunk2s = chunk_for(o2s * n_cu * kBlock2s / kWave);
-        h->chunk2t = chunk_for(o2t * n_cu * kBlock2t / kWave);
         h->G1 = grid(o1, kBlock1, h->chunk1);
         h->G2s = grid(o2s, kBlock2s, h->chunk2s);
-        h->G2t = grid(o2t, kBlock2t, h->chunk2t);
         // the fused pass keeps the block's instrumental sums and the instrumental part of xt
         // in LDS (160 KiB per CU)
         h->lds12_bytes = sizeof(double) * (2 * (size_t)g.I + 1);
@@ -1153,6 +1211,8 @@ gsr_status gsr_destroy(gsr_handle* h) {
     dfree(h->attT64);
     dfree(h->rowT);
     dfree(h->tT);
+    dfree(h->att_seg);
+    dfree(h->att_part);
     dfree(h->xt);
     dfree(h->part_ig);
     dfree(h->p64);

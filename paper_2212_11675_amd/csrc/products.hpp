@@ -650,61 +650,87 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
 }
 
 // ---------------------------------------------------------------------------------------
-// aprod 2, attitude pass over the library-owned copy sorted by attitude start t:
-//   attT[k][4 a + j] = A[row_k, 5 + 4 a + j],  rowT[k] = row_k,  tT[k] = att[row_k].
-// Lane q takes column t + q of the three axes; runs of equal t are reduced in registers and
-// added to x once per run and wave chunk (atomic: chunks meet inside a run).
+// aprod 2, attitude columns, over the library-owned copy of the attitude coefficients in
+// the order (group, row slice, t).  The attitude starts are cut into nb buckets of W knots
+// and the rows into slices of consecutive rows, dealt round-robin to the dies; group
+// G = b kXcd + x holds the rows of bucket b in the slices of die x.  Block G (placed by the
+// dispatcher on die G % kXcd) takes group G and sums the columns t + q of its bucket, three
+// axes, in LDS; its waves move through the die's slices in step with the die's other blocks,
+// so the u~ values they gather at any time come from one slice, which the die's L2 holds.
+// The block's sums go to part[G] (kAxes rows of lw = W + kParAxis - 1 columns), added to x by
+// k_att_reduce.  Row k of the copy (tile k / kStepRows): attT = A[row_k, 5 + 4 a + j],
+// rowT[k] = row_k, tL[k] = att[row_k] - b W; group G is rows seg[G] .. seg[G + 1] - 1.
+constexpr int kXcd = 8;  // accelerator dies; the dispatcher places block i on die i % 8
+constexpr int kBlockAtt = 512;
+constexpr int kAttChunkTiles = 4;  // wave steps per chunk (chunks dealt to the waves in turn)
+
 template <typename VT, int MODE>
-static __global__ __launch_bounds__(256) void k_aprod2_att(
+static __global__ __launch_bounds__(kBlockAtt) void k_aprod2_att(
     Geo g, const VT* __restrict__ attT, const int32_t* __restrict__ rowT,
-    const int32_t* __restrict__ tT, const double* __restrict__ y, double* __restrict__ x,
-    const LsqrState* __restrict__ st, int chunk_rows) {
+    const int32_t* __restrict__ tL, const int64_t* __restrict__ seg, int lw,
+    const double* __restrict__ y, double* __restrict__ part, const LsqrState* __restrict__ st) {
     if ((MODE == A2_LSQR || MODE == A2_LSQR_T) && st->stop) return;
+    extern __shared__ double acc[];  // [kAxes][lw]
+    for (int i = threadIdx.x; i < kAxes * lw; i += blockDim.x) acc[i] = 0.0;
+    __syncthreads();
     const double ysc = a2_scale<MODE>(st);
     const int lane = threadIdx.x % kWave, rg = lane / kQuad, q = lane % kQuad;
-    const int wpb = blockDim.x / kWave;
-    const int64_t nchunks = (g.m + chunk_rows - 1) / chunk_rows;
-    double* __restrict__ xatt = x + g.att0 + q;
-    auto flush = [&](int32_t key, const double (&t)[3]) {
-        if (rg != 0) return;
+    const int wave = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+    const int64_t lo = seg[blockIdx.x], hi = seg[blockIdx.x + 1];
+    if (lo < hi) {
+        const int64_t t_beg = lo / kStepRows, t_end = (hi + kStepRows - 1) / kStepRows;
+        for (int64_t c0 = t_beg + (int64_t)wave * kAttChunkTiles; c0 < t_end;
+             c0 += (int64_t)wpb * kAttChunkTiles) {
+            const int64_t c1 = min(c0 + kAttChunkTiles, t_end);
+            constexpr int U = 2;  // wave steps loaded before any is added
+            for (int64_t tl = c0; tl < c1; tl += U) {
+                int32_t col[U];
+                double va[U][kAxes], yy[U];
+                bool valid[U];
 #pragma unroll
-        for (int ax = 0; ax < kAxes; ++ax) atomic_add_f64(xatt + (int64_t)ax * g.T + key, t[ax]);
-    };
-    for (int64_t ch = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; ch < nchunks;
-         ch += (int64_t)gridDim.x * wpb) {
-        const int64_t k_end = min((ch + 1) * (int64_t)chunk_rows, g.m);
-        const int64_t k_beg = ch * (int64_t)chunk_rows;
-        double acc[3] = {0.0, 0.0, 0.0};
-        int32_t ckey = -1;
-        constexpr int U = 2;  // row steps loaded before any is reduced
-        for (int64_t k0 = k_beg; k0 < k_end; k0 += kStepRows * U) {
-            int32_t kt[U];
-            double va[U][kAxes], yy[U];
-            bool valid[U];
-#pragma unroll
-            for (int w = 0; w < U; ++w) {
-                const int64_t k = k0 + w * kStepRows + rg;
-                valid[w] = k < k_end;
-                const int64_t kk = valid[w] ? k : k_beg;  // in-bounds stand-in
-                kt[w] = tT[kk];
-                yy[w] = (MODE == A2_SQ) ? 0.0 : ysc * y[rowT[kk]];
-                const int64_t tile = (k0 + w * kStepRows < k_end) ? k0 / kStepRows + w
-                                                                  : k_beg / kStepRows;
-                ld_att_tile(attT, tile, lane, va[w]);
-            }
-#pragma unroll
-            for (int w = 0; w < U; ++w) {
-                int32_t key = -1;
-                double v[3] = {0.0, 0.0, 0.0};
-                if (valid[w]) {
-                    key = kt[w];
-#pragma unroll
-                    for (int ax = 0; ax < kAxes; ++ax) v[ax] = contrib<MODE>(va[w][ax], yy[w]);
+                for (int w = 0; w < U; ++w) {
+                    const int64_t tile = (tl + w < c1) ? tl + w : c0;
+                    const int64_t k = tile * kStepRows + rg;
+                    valid[w] = tl + w < c1 && k >= lo && k < hi;
+                    const int64_t kk = valid[w] ? k : lo;  // in-bounds stand-in
+                    col[w] = tL[kk] + q;
+                    yy[w] = (MODE == A2_SQ) ? 0.0 : ysc * y[rowT[kk]];
+                    ld_att_tile(attT, tile, lane, va[w]);
                 }
-                run_step<3, kQuad>(key, v, acc, ckey, flush);
+#pragma unroll
+                for (int w = 0; w < U; ++w) {
+                    if (!valid[w]) continue;
+#pragma unroll
+                    for (int ax = 0; ax < kAxes; ++ax)
+                        atomicAdd(acc + ax * lw + col[w], contrib<MODE>(va[w][ax], yy[w]));
+                }
             }
         }
-        run_close<3, kQuad>(acc, ckey, flush);
+    }
+    __syncthreads();
+    double* __restrict__ dst = part + (int64_t)blockIdx.x * kAxes * lw;
+    for (int i = threadIdx.x; i < kAxes * lw; i += blockDim.x) dst[i] = acc[i];
+}
+
+// x[att0 + a T + c] += the sums of column c over the groups whose bucket covers it: bucket
+// c / W of every die and the buckets before it whose columns reach c (the previous one for
+// the first kParAxis - 1 columns of a bucket when W >= kParAxis - 1, more when W is smaller).
+// check_stop: nothing is done once the LSQR stop flag is set.
+static __global__ void k_att_reduce(Geo g, int w, int lw, const double* __restrict__ part,
+                                    double* __restrict__ x, const LsqrState* __restrict__ st,
+                                    int check_stop) {
+    if (check_stop && st->stop) return;
+    const int64_t n = (int64_t)kAxes * g.T;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int64_t ax = e / g.T, c = e - ax * g.T;
+        double sum = 0.0;
+        for (int64_t b = c / w; b >= 0 && c - b * w < lw; --b) {
+            const double* __restrict__ p = part + (b * kXcd * kAxes + ax) * lw + (c - b * w);
+#pragma unroll
+            for (int d = 0; d < kXcd; ++d) sum += p[(int64_t)d * kAxes * lw];
+        }
+        x[g.att0 + e] += sum;
     }
 }
 
@@ -730,6 +756,43 @@ static __global__ void k_iota(int64_t m, int32_t* __restrict__ v) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
         v[i] = (int32_t)i;
+}
+
+// Sort key of row i for the attitude copy: group G = (t / w) kXcd + (slice % kXcd) above the
+// slice's number on its die (sbits wide) above t - (t / w) w (tbits wide); slice = i >> shift.
+static __global__ void k_att_keys(int64_t m, int shift, int w, int sbits, int tbits,
+                                  const int32_t* __restrict__ att, uint64_t* __restrict__ key) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const int64_t slice = i >> shift, t = att[i], b = t / w;
+        const uint64_t grp = (uint64_t)(b * kXcd + slice % kXcd);
+        key[i] = (((grp << sbits) | (uint64_t)(slice / kXcd)) << tbits) | (uint64_t)(t - b * w);
+    }
+}
+
+// seg[G] = first position of group G in the sorted keys (G = 0 .. ng; seg[ng] = m).
+static __global__ void k_att_seg(int64_t m, int ng, int low_bits, const uint64_t* __restrict__ key,
+                                 int64_t* __restrict__ seg) {
+    const int grp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (grp > ng) return;
+    const uint64_t target = (uint64_t)grp << low_bits;
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (key[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    seg[grp] = lo;
+}
+
+// The column offset in the bucket, t - b w, from each sorted key.
+static __global__ void k_att_tl(int64_t m, uint64_t mask, const uint64_t* __restrict__ key,
+                                int32_t* __restrict__ tl) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+        tl[i] = (int32_t)(key[i] & mask);
 }
 
 }  // namespace gsr
