@@ -967,7 +967,7 @@ std::map<std::tuple<int, int64_t, int>, Tuning> g_tune_cache;
 template <typename T>
 gsr_status balloc(T** p, size_t count) {
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    hipError_t e = device_alloc((void**)p, count * sizeof(T));
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(GSR_E_NOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));

@@ -89,6 +89,19 @@ int grid_for(int64_t items, int per_block, int max_blocks) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, max_blocks));
 }
 
+// Arrays of 1 GiB and more are asked for as physically contiguous memory first, plain
+// hipMalloc when that fails.  Measured: with ordinary allocations the fused row pass over
+// tens of GB of row tiles ran up to 10% slower in a process started right after another one
+// had used and freed most of the device memory, and at full speed with contiguous ones.
+hipError_t device_alloc(void** p, size_t bytes) {
+    if (bytes >= (size_t(1) << 30)) {
+        if (hipExtMallocWithFlags(p, bytes, hipDeviceMallocContiguous) == hipSuccess)
+            return hipSuccess;
+        (void)hipGetLastError();
+    }
+    return hipMalloc(p, bytes);
+}
+
 }  // namespace gsr
 
 #define HIP_TRY(call)                                      \
@@ -182,7 +195,7 @@ constexpr int kGraphIters = 16;
 template <typename T>
 gsr_status dalloc(T** p, size_t count) {
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    hipError_t e = device_alloc((void**)p, count * sizeof(T));
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(GSR_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
@@ -343,11 +356,13 @@ gsr_status colnorm(gsr_handle* h, const VT* vals, const VT* attT, double* p, hip
 
 // The attitude copy (see k_aprod2_att): rows sorted by (group, slice on its die, t - b W)
 // with a stable radix sort, the group boundaries, and the attitude coefficients gathered in
-// that order.  Buckets: kAttBuckets per die, fewer when T is small, more when a bucket's sums
-// would outgrow kAttLdsBytes.  Slices: 2^17 rows (1 MiB of binary64 u~, well inside a die's
-// 4 MiB L2 beside the streamed coefficients), shorter for small systems so that every die
-// gets slices.  Synchronizes.
-constexpr int kAttBuckets = 128;
+// that order.  Buckets: kAttBuckets per die (512 blocks of kBlockAtt threads on 256 compute
+// units, 16 waves per unit: measured faster than 8, whose loads in flight do not fill the
+// memory pipe, and than 32, whose gathers and streamed lines crowd the slice out of L2), fewer
+// when T is small, more when a bucket's sums would outgrow kAttLdsBytes.  Slices: 2^16 rows
+// (512 KiB of binary64 u~, well inside a die's 4 MiB L2 beside the streamed coefficients),
+// shorter for small systems so that every die gets slices.  Synchronizes.
+constexpr int kAttBuckets = 64;
 constexpr size_t kAttLdsBytes = 40 * 1024;
 
 gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
@@ -378,7 +393,7 @@ gsr_status build_att_order(gsr_handle* h, hipStream_t s) {
     GSR_TRY(dalloc(&h->att_seg, (size_t)h->att_ng + 1));
     GSR_TRY(dalloc(&h->att_part, (size_t)h->att_ng * kAxes * h->att_lw));
     if (m == 0) return GSR_OK;
-    int shift = 17;
+    int shift = 16;
     while (shift > 8 && (m >> shift) < 64) --shift;
     const int sbits = bits_for(((m - 1) >> shift) / kXcd);
     const int tbits = bits_for(w - 1);

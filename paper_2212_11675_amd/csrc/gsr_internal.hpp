@@ -22,5 +22,7 @@ gsr_status check_device(int* dev, int* n_cu);
 gsr_status check_dims(const gsr_dims* d);
 Geo make_geo(const gsr_dims* d);
 int grid_for(int64_t items, int per_block, int max_blocks);
+// Device memory for the library's arrays (hipMalloc semantics; free with hipFree).
+hipError_t device_alloc(void** p, size_t bytes);
 
 }  // namespace gsr
