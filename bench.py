@@ -823,8 +823,8 @@ def main() -> None:
         pb = pass_bytes(m, n, shape, fused)
         gbps1 = pb["pass1"] / (ms1 * 1e-3) / 1e9
         gbps2 = pb["pass2"] / (ms2 * 1e-3) / 1e9
-        names = (("k_aprod12", "k_reduce_partials + k_aprod2_att") if fused
-                 else ("k_aprod1", "k_aprod2_star + k_reduce_partials + k_aprod2_att"))
+        att = "k_reduce_partials + k_aprod2_att + k_att_reduce"
+        names = ("k_aprod12", att) if fused else ("k_aprod1", "k_aprod2_star + " + att)
         dom = 0 if ms1 >= ms2 else 1
         gb, msd = (gbps1, ms1) if dom == 0 else (gbps2, ms2)
         copy_gbps = copy_bandwidth()

@@ -611,6 +611,45 @@ def test_unsorted_repeated_instrumental_and_empty_stars(shape):
     h.close()
 
 
+@pytest.mark.parametrize("n_dfa", [150_000, 4], ids=["dfa150k", "dfa4"])
+def test_attitude_buckets_wide_and_narrow(n_dfa):
+    """The attitude pass cuts the attitude starts into buckets whose column sums one block
+    holds in LDS: with 150,000 knots per axis more buckets than the default number are needed
+    (a bucket's sums would not fit), with 4 knots every row has t = 0 and falls in one bucket
+    of width 1 (its columns reach three buckets further).  Products (binary64 and binary32),
+    preconditioner with empty attitude columns, and 5 PC-LSQR iterations against the oracle."""
+    shape = synth.Shape(2000, 20, 40, n_dfa, 30, seed=141)
+    print(f"[buckets] n_dfa={n_dfa}", flush=True)
+    sysd = synth.system(shape)
+    S = oracle_system(sysd)
+    h, _ = open_system(sysd, allow_empty_cols=True, build_f32=True)
+    rng = np.random.default_rng(142)
+    x, y0 = rng.standard_normal(S.n), rng.standard_normal(S.m)
+    yd = cuda(y0)
+    gsr.gsr_aprod1(h, cuda(x), yd)
+    assert_close_scaled(host(yd), S.aprod1(x, y0), 1e-13)
+    y, x0 = rng.standard_normal(S.m), rng.standard_normal(S.n)
+    xd = cuda(x0)
+    gsr.gsr_aprod2(h, cuda(y), xd)
+    assert_close_scaled(host(xd), S.aprod2(y, x0), 1e-13)
+    S32 = S.with_vals(sysd["vals"].astype(np.float32).astype(np.float64))
+    xd = cuda(x0)
+    gsr.gsr_aprod2_f32v(h, cuda(y), xd)
+    assert_close_scaled(host(xd), S32.aprod2(y, x0), 1e-13)
+    p = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    gsr.gsr_precond(h, p)
+    po = S.colnorm()
+    assert np.array_equal(host(p) == 0, po == 0)
+    np.testing.assert_allclose(host(p), po, rtol=1e-12, atol=0)
+    b = S.aprod1(synth.x_true(shape)) + synth.noise(shape)
+    xg = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    info = gsr.gsr_lsqr_solve(h, cuda(b), xg, gsr.solve_opts(itnlim=5, fixed_iters=True))
+    xo, io = S.lsqr(b, itnlim=5, fixed=True)
+    assert info["itn"] == io["itn"] == 5
+    assert rel(host(xg), xo) <= 1e-10
+    h.close()
+
+
 def test_full_size_binary32_products_and_refinement_vs_oracle():
     """The 2e7-row system at its real size with binary32-stored coefficients: the binary32
     products and preconditioner against the oracle on the binary32-rounded coefficients, and
