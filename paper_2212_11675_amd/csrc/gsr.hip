@@ -1081,16 +1081,18 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         };
         // rows per wave chunk: at most 1024, and sized so that every wave of the persistent
         // grid gets (nearly) the same number of chunks (small systems: at least 4 per wave)
-        auto chunk_for = [&](int waves) {
+        // rows per wave chunk: about `cap`, the same number of chunks for every wave, at
+        // least four chunks per wave for small systems
+        auto chunk_for = [&](int waves, int64_t cap = 1024) {
             const int64_t w = std::max(waves, 1);
             int64_t c;
-            if (g.m >= 4 * 1024 * w) {
-                const int64_t per = (g.m + 1024 * w - 1) / (1024 * w);  // chunks per wave
+            if (g.m >= 4 * cap * w) {
+                const int64_t per = (g.m + cap * w - 1) / (cap * w);  // chunks per wave
                 c = (g.m + w * per - 1) / (w * per);
             } else {
                 c = g.m / (4 * w);
             }
-            c = std::max<int64_t>(kStepRows, std::min<int64_t>(1024, c));
+            c = std::max<int64_t>(kStepRows, std::min<int64_t>(cap, c));
             return (int)((c + kStepRows - 1) / kStepRows * kStepRows);
         };
         auto grid = [&](int per_cu, int threads, int chunk) {
@@ -1110,7 +1112,9 @@ gsr_status gsr_lsqr_setup(const gsr_dims* dims, const double* vals, const int32_
         h->fused = h->lds2 && h->lds12_bytes <= 160 * 1024;
         if (h->fused) {
             const int o12 = occ((const void*)k_aprod12<double, kU12>, 1024, h->lds12_bytes);
-            h->chunk12 = chunk_for(o12 * n_cu * 1024 / kWave);
+            // 2,048-row chunks: measured 3 % faster than 1,024 at 2e8 rows (fewer chunk
+            // switches, each a fresh stream start)
+            h->chunk12 = chunk_for(o12 * n_cu * 1024 / kWave, 2048);
             h->G12 = grid(o12, 1024, h->chunk12);
         }
     }
