@@ -662,7 +662,7 @@ static __global__ __launch_bounds__(1024) void k_aprod12(
 // rowT[k] = row_k, tL[k] = att[row_k] - b W; group G is rows seg[G] .. seg[G + 1] - 1.
 constexpr int kXcd = 8;  // accelerator dies; the dispatcher places block i on die i % 8
 constexpr int kBlockAtt = 512;
-constexpr int kAttChunkTiles = 4;  // wave steps per chunk (chunks dealt to the waves in turn)
+constexpr int kAttChunkTiles = 2;  // wave steps per chunk (chunks dealt to the waves in turn)
 
 template <typename VT, int MODE>
 static __global__ __launch_bounds__(kBlockAtt) void k_aprod2_att(
