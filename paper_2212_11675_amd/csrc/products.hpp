@@ -317,6 +317,14 @@ static __global__ __launch_bounds__(512) void k_aprod1(
             double sum = 0.0;
             double a[6];
             int32_t s, t, ia, ib;
+            // the row's old y (or b) is loaded with the coefficients, not after the gathers
+            // (one memory round trip fewer per step)
+            const int64_t rr = valid ? r : r_end - 1;  // in-bounds stand-in row
+            double yo = 0.0;
+            if (MODE == A1_RESID)
+                yo = b[rr];
+            else if (MODE == A1_ADD || (kLsqr && ys != 0.0))
+                yo = y[rr];
             if (TILED) {  // the whole step's tile (rows past m are padding inside it)
                 ld_tile(tiles, r0 / kStepRows, lane, a);
                 ld_tile_idx(tiles, r0 / kStepRows, lane, s, t, ia, ib);
@@ -346,11 +354,11 @@ static __global__ __launch_bounds__(512) void k_aprod1(
             sum = quad_sum(sum);
             if (valid && q == 0) {
                 if (MODE == A1_ADD) {
-                    y[r] += sum;
+                    y[r] = yo + sum;
                 } else if (MODE == A1_RESID) {
-                    y[r] = b[r] - sum;
+                    y[r] = yo - sum;
                 } else {
-                    const double u = (ys != 0.0) ? xs * sum - ys * y[r] : xs * sum;
+                    const double u = (ys != 0.0) ? xs * sum - ys * yo : xs * sum;
                     y[r] = u;
                     acc = fma(u, u, acc);
                 }
