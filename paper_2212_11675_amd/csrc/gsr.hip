@@ -454,7 +454,7 @@ void mark(hipEvent_t e, hipStream_t s) {
 // global), then the instrumental/global reduction and the attitude pass (s += A_att^T u~).
 // The fused row pass (u-step of the forward solve, or with TRANS the v-step of the adjoint
 // solve with its pending z/w update in ww/zz), then the instrumental/global block sums and
-// the attitude columns of s from the t-ordered copy.  Sum-of-squares partials go to `parts`.
+// the attitude columns of s from the attitude copy.  Sum-of-squares partials go to `parts`.
 constexpr int kU12 = 1;  // row steps per load batch of the fused pass (measured best)
 template <typename VT, bool TRANS = false, bool INIT = false>
 void launch_fused(const gsr_handle* h, const VT* vals, const VT* attT, double* u, double* s_acc,

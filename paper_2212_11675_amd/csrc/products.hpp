@@ -137,7 +137,7 @@ static __global__ void k_make_itiles(int64_t m, int64_t ntiles, const int32_t* _
     }
 }
 
-// Attitude tiles (the t-ordered copy): kStepRows rows of 12 attitude coefficients; lane
+// Attitude tiles (the attitude copy): kStepRows rows of 12 attitude coefficients; lane
 // (rg, q) needs column t + q of the three axes of row rg: a group [rg][q][2] (axes 0, 1)
 // followed by a group [rg][q] (axis 2).  Padding rows are zero.
 constexpr int kTileAtt = kStepRows * kAxes * kParAxis;  // 192 coefficients per tile
@@ -508,7 +508,7 @@ static __global__ void k_reduce_partials(int ncols, int nblocks, const double* _
 //   u~[r] = sv (A xt)[r] - alpha su u~[r]            (xt = p o v~, the previous v-step)
 //   s[c] += A[r,c] u~[r]   for the astrometric, instrumental and global columns
 // s is accumulated unnormalized (1/beta is applied by the vector step once beta is known);
-// the attitude columns of s come from k_aprod2_att on the t-ordered copy.  Block partials:
+// the attitude columns of s come from k_aprod2_att on the attitude copy.  Block partials:
 // sum u~^2 -> partials[block], instrumental/global sums -> part[block][n_instr + 1].
 // U row steps are loaded before any of them is reduced.
 //
@@ -742,8 +742,8 @@ static __global__ void k_att_reduce(Geo g, int w, int lw, const double* __restri
     }
 }
 
-// Library-owned attitude copy in t order, as attitude tiles: row k of the copy is row
-// rowT[k] of the system; ntiles * kTileAtt elements.
+// Library-owned attitude copy (the order of k_aprod2_att), as attitude tiles: row k of the
+// copy is row rowT[k] of the system; ntiles * kTileAtt elements.
 template <typename VT>
 static __global__ void k_gather_att(int64_t m, int64_t ntiles, const VT* __restrict__ vals,
                                     const int32_t* __restrict__ rowT, VT* __restrict__ attT) {
