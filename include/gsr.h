@@ -153,8 +153,9 @@ const char *gsr_last_error(void);
  * Computes the preconditioner p_j = 1/||A e_j||_2 (0 for an all-zero column) on the device.
  * Ownership: the four arrays stay the caller's and must stay allocated and unchanged while
  * the handle lives; the library also builds its own copies of them at setup (coefficient and
- * index tiles, a copy ordered by attitude start, binary32 copies), so a change made after
- * setup would reach only some of the products.  Set up a new handle instead.
+ * index tiles, a copy of the attitude coefficients grouped by attitude start, binary32
+ * copies), so a change made after setup would reach only some of the products.  Set up a
+ * new handle instead (or bring new values in with gsr_update_values).
  * Synchronizes `stream`.  Errors: GSR_E_INVAL, GSR_E_LAYOUT, GSR_E_NOMEM, GSR_E_HIP,
  * GSR_E_NODEVICE.
  */
@@ -262,7 +263,7 @@ gsr_status gsr_grad_vals(gsr_handle *h, const double *r, const double *mu, const
 
 /*
  * New coefficient values for the handle's system, same index map (star, att, instr) and
- * sizes: the library's copies of the coefficients (row tiles, the copy ordered by attitude
+ * sizes: the library's copies of the coefficients (row tiles, the copy grouped by attitude
  * start, the binary32 copies when built) are rebuilt in place and the preconditioner is
  * recomputed (Section 2), without the sort and the allocations of gsr_lsqr_setup.  For
  * callers that change the coefficients between solves (the differentiation form's training
