@@ -3,7 +3,7 @@
 Tolerances: the products differ from the oracle only in summation order (fused multiply-add
 and device atomics), so they are compared elementwise to 1e-12 of the largest entry; LSQR
 iterates to ||x - x_oracle|| / ||x_oracle|| <= 1e-10 (binary64) and the refined mixed-precision
-solution to 1e-8, as the benchmark spec's tolerances state.
+solution to 1e-8, the relative solution error the precision form is required to reach.
 """
 import numpy as np
 import pytest
